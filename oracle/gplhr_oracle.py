@@ -1,0 +1,336 @@
+"""Plain FP64 CPU reference implementation of GPLHR -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  The product path (the HIP library and its Python binding) never
+calls it, and shares no code with it.
+
+It implements the Schur-vector form of the Generalized Preconditioned Locally
+Harmonic Residual method (Vecharynski, Yang, Xue; Algorithm 2 of Section 3.5,
+"The GPLHR algorithm") step by step, with numpy/scipy primitives:
+
+* sparse products:  scipy.sparse CSR times a dense block,
+* ``orth``:         Householder QR (scipy.linalg.qr, economic),
+* ``ordqz``:        complex QZ (scipy.linalg.qz) reordered by adjacent swaps
+                    (LAPACK ztgexc) so that |alpha/beta - sigma| ascends,
+* small matrices:   numpy dense FP64 complex.
+
+Readings taken where the paper is silent or inconsistent (each is listed in
+the design doc as well):
+
+* ``orth`` (footnote of Algorithm 1) is any orthonormalisation of the span; we
+  use Householder QR and normalise to the Q factor whose triangular factor has
+  a positive real diagonal (unique for full rank).
+* ordqz factors are unique only up to unimodular column scalings of Y_L, Y_R,
+  and the Q-free factors M_A, M_B depend on that scaling through the
+  1 - R_B(j,j) term of eq. G1_fix.  We scale so that R_B has a real
+  non-negative diagonal (the choice under which M_B tends to I for B = I, as
+  Section 3.3 remarks).  With both conventions fixed, every iterate is a
+  well-defined function of the inputs (up to rounding).
+* Test-basis step of Algorithm 2: the paper orthonormalises and then subtracts
+  Q (Q^* Qhat), which would leave U non-orthonormal although Section 3.3
+  requires orthonormal U.  We project first and orthonormalise afterwards.
+* Ordering ties in ordqz are broken by QZ position (stable); beta = 0 sorts as
+  +infinity.
+* Convergence: relative eigen-residual ||A x - lambda B x|| / ||A x|| of the
+  Rayleigh-Ritz eigenpairs of (V^* A V, V^* B V) (Section 5.1 uses this
+  measure, with eigenvectors obtained from V by Rayleigh-Ritz, Section 2.1).
+* First iteration: P is empty, so the trial space has (m+2)b columns.
+* Block width b may exceed k; the k leading pairs decide convergence.
+
+Parity pins: see tests/test_oracle.py (closed-form spectrum of the 2-D
+upwind stencil, dense QZ eigenvalues of small pencils, the Schur-form and
+Q-free-form invariants of Section 2, Propositions 3.1 and 3.2, the residual
+identity that follows Algorithm 2, exact-preconditioner and full-space special
+cases).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from scipy.linalg.lapack import ztgexc
+
+
+# --------------------------------------------------------------------------
+# small dense building blocks
+# --------------------------------------------------------------------------
+
+def _unit_phase(z: np.ndarray) -> np.ndarray:
+    a = np.abs(z)
+    out = np.ones_like(z)
+    nz = a > 0
+    out[nz] = z[nz] / a[nz]
+    return out
+
+
+def orth(X: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the columns of X (footnote of Algorithm 1 leaves
+    the procedure open).  Householder QR, with the columns of the Q factor
+    rescaled so that the triangular factor has a positive real diagonal: the
+    unique 'Q' of X = QR for full-rank X."""
+    Qx, Rx = sla.qr(X, mode="economic")
+    return Qx * _unit_phase(np.diag(Rx))[None, :]
+
+
+def _dist(a: complex, b: complex, sigma: complex) -> float:
+    if b == 0:
+        return np.inf
+    return abs(a / b - sigma)
+
+
+def ordqz(F: np.ndarray, G: np.ndarray, sigma: complex):
+    """Full generalized Schur form of (F, G), ordered so that
+    |R_A(i,i)/R_B(i,i) - sigma| is non-decreasing (footnote to step 2 of
+    Algorithm 2).  Returns (R_A, R_B, Y_L, Y_R) with F Y_R = Y_L R_A and
+    G Y_R = Y_L R_B."""
+    RA, RB, YL, YR = sla.qz(F, G, output="complex")
+    s = F.shape[0]
+    for pos in range(s):
+        d = [_dist(RA[j, j], RB[j, j], sigma) for j in range(pos, s)]
+        j = pos + int(np.argmin(d))          # first minimum: ties keep QZ order
+        if j != pos:
+            # ztgexc moves the diagonal entry at (1-based) ifst to ilst.
+            RA, RB, YL, YR, info = ztgexc(RA, RB, YL, YR, j + 1, pos + 1)
+            if info != 0:
+                raise RuntimeError(f"ztgexc failed (info={info})")
+    # The factors are unique only up to unimodular column scalings of Y_L and
+    # Y_R; M_A, M_B (through G1 of eq. G1_fix) depend on that choice.  Fix it:
+    # scale Y_L so that R_B has a real non-negative diagonal (R_A's diagonal
+    # real positive where R_B(j,j) = 0).  With this choice M_B tends to I for
+    # B = I, as Section 3.3 states.
+    dB, dA = np.diag(RB), np.diag(RA)
+    th = np.where(np.abs(dB) > 0, _unit_phase(dB), _unit_phase(dA))
+    YL = YL * th[None, :]
+    RA = th.conj()[:, None] * RA
+    RB = th.conj()[:, None] * RB
+    return RA, RB, YL, YR
+
+
+def q_free_factors(RA: np.ndarray, RB: np.ndarray):
+    """M_A, M_B of the 'Q-free' Schur form (Theorem 2.2, eq. M) with the
+    diagonal G1, G2 of eqs. G1_fix and G2_fix (Section 2.2).  Also returns
+    G = R_A G1 + R_B G2 (unit upper triangular by Lemma 2.1)."""
+    k = RA.shape[0]
+    g1 = np.zeros(k, dtype=complex)
+    g2 = np.zeros(k, dtype=complex)
+    for j in range(k):
+        a, b = RA[j, j], RB[j, j]
+        if abs(a) < abs(b):
+            g1[j] = 0.0
+            g2[j] = 1.0 / b
+        else:
+            g1[j] = (1.0 - b) / a
+            g2[j] = 1.0
+    G = RA @ np.diag(g1) + RB @ np.diag(g2)
+    Ginv_RA = sla.solve_triangular(G, RA, lower=False)
+    MA = np.diag(g2) @ Ginv_RA
+    MB = np.eye(k) - np.diag(g1) @ Ginv_RA
+    return MA, MB, G
+
+
+# --------------------------------------------------------------------------
+# preconditioners T ~ (A - sigma B)^{-1}  (Section 4)
+# --------------------------------------------------------------------------
+
+def make_preconditioner(C: sp.csr_matrix, kind: str, sweeps: int = 3, omega: float = 0.7
+                        ) -> Callable[[np.ndarray], np.ndarray]:
+    """T applied to a block.
+
+    kind = "identity": T = I.
+    kind = "diag":     T = diag(C)^{-1}.
+    kind = "jacobi":   ``sweeps`` damped Jacobi steps on C w = r from w_0 = 0:
+                       w_{t+1} = w_t + omega diag(C)^{-1} (r - C w_t).
+    kind = "exact":    T = C^{-1} by sparse LU.
+    """
+    if kind == "identity":
+        return lambda R: R.copy()
+    d = C.diagonal()
+    if kind == "diag":
+        return lambda R: R / d[:, None]
+    if kind == "jacobi":
+        def apply(R):
+            Wb = np.zeros_like(R)
+            for _ in range(sweeps):
+                Wb = Wb + omega * (R - C @ Wb) / d[:, None]
+            return Wb
+        return apply
+    if kind == "exact":
+        lu = spla.splu(sp.csc_matrix(C))
+        return lambda R: lu.solve(np.ascontiguousarray(R))
+    raise ValueError(kind)
+
+
+# --------------------------------------------------------------------------
+# convergence measure
+# --------------------------------------------------------------------------
+
+def ritz_pairs(A, B, V: np.ndarray, sigma: complex):
+    """Rayleigh-Ritz eigenpairs of (A, B) on span(V) (Section 2.1), ordered by
+    |lambda - sigma|, with relative eigen-residuals ||A x - lambda B x||/||A x||
+    (Section 5.1)."""
+    AV = A @ V
+    BV = V if B is None else B @ V
+    lam, Zr = sla.eig(V.conj().T @ AV, V.conj().T @ BV)
+    order = np.argsort(np.abs(lam - sigma), kind="stable")
+    lam = lam[order]
+    Zr = Zr[:, order]
+    Zr = Zr / np.linalg.norm(Zr, axis=0)
+    Ax = AV @ Zr
+    Bx = BV @ Zr
+    res = np.linalg.norm(Ax - Bx * lam[None, :], axis=0)
+    rho = res / np.linalg.norm(Ax, axis=0)
+    return lam, V @ Zr, rho, res
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2
+# --------------------------------------------------------------------------
+
+@dataclass
+class GplhrResult:
+    V: np.ndarray
+    Q: np.ndarray
+    RA: np.ndarray
+    RB: np.ndarray
+    MA: np.ndarray
+    MB: np.ndarray
+    lam: np.ndarray          # Rayleigh-Ritz eigenvalues on span(V), nearest sigma first
+    X: np.ndarray            # matching unit eigenvectors
+    rho: np.ndarray          # relative eigen-residuals
+    iterations: int
+    converged: bool
+    history: list = field(default_factory=list)   # max rho over the k leading pairs, per check
+    lam_history: list = field(default_factory=list)
+    trace: list = field(default_factory=list)     # optional per-iteration internals
+
+    @property
+    def R(self) -> np.ndarray:
+        """Standard problem output R = M_B^{-1} M_A (last line of Algorithm 2)."""
+        return np.linalg.solve(self.MB, self.MA)
+
+
+def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
+          m: int = 1, tol: float = 1e-10, maxit: int = 500, p_mode: str = "thick",
+          keep_trace: bool = False, callback: Optional[Callable] = None) -> GplhrResult:
+    """Algorithm 2 (GPLHR, Schur-vector form).
+
+    A, B     scipy sparse n-by-n (B None: standard problem, B = I).
+    sigma    target shift, not an eigenvalue.
+    k        number of wanted eigenpairs; the block width b = V0.shape[1] >= k.
+    precond  callable applying T ~ (A - sigma B)^{-1} to a block.
+    m        Krylov-Arnoldi depth (number of S blocks).
+    p_mode   "thick": P = Z Ybar_R(:, b+1:2b) (eq. P1, step 28);
+             "none":  no P block (trial space of eq. trial_partial).
+    """
+    A = sp.csr_matrix(A)
+    std = B is None
+    Bm = sp.identity(A.shape[0], format="csr", dtype=complex) if std else sp.csr_matrix(B)
+    C = (A - sigma * Bm).tocsr()
+    b = V0.shape[1]
+    if k > b:
+        raise ValueError("k must not exceed the block width")
+
+    def Bx(X):
+        return X if std else Bm @ X
+
+    # step 1
+    V = orth(V0)
+    Q = orth(C @ V)
+    P = None
+    # steps 2-4
+    RA, RB, YL, YR = ordqz(Q.conj().T @ (A @ V), Q.conj().T @ Bx(V), sigma)
+    V = V @ YR
+    Q = Q @ YL
+    MA, MB, _ = q_free_factors(RA, RB)
+
+    history, lam_history, trace = [], [], []
+    it = 0
+    while True:
+        lam, X, rho, _ = ritz_pairs(A, None if std else Bm, V, sigma)
+        history.append(float(np.max(rho[:k])))
+        lam_history.append(lam[:k].copy())
+        if callback is not None:
+            callback(it, lam, rho)
+        if np.max(rho[:k]) <= tol or it >= maxit:
+            break
+        it += 1
+
+        def proj_V(X):
+            return X - V @ (V.conj().T @ X)
+
+        def proj_left(X):   # I - QQ^* for B != I, I - VV^* for B = I
+            Y = V if std else Q
+            return X - Y @ (Y.conj().T @ X)
+
+        # steps 6-10: projected preconditioned residual
+        if not std:
+            WA = A @ V - Q @ RA
+            WB = Bm @ V - Q @ RB
+            W = proj_V(precond(proj_left(WA @ MB - WB @ MA)))
+        else:
+            W = proj_V(precond(proj_left(A @ V @ MB - V @ MA)))
+        # step 12
+        W = orth(W)
+        S_prev = W
+        S = np.zeros((V.shape[0], 0), dtype=complex)
+        # steps 13-21: Krylov-Arnoldi blocks
+        for _ in range(m):
+            Sl = proj_V(precond(proj_left(A @ S_prev @ MB - Bx(S_prev) @ MA)))
+            Sl = Sl - W @ (W.conj().T @ Sl)
+            Sl = Sl - S @ (S.conj().T @ Sl)
+            Sl = orth(Sl)
+            S = np.hstack([S, Sl])
+            S_prev = Sl
+        # step 22
+        if P is not None:
+            P = P - V @ (V.conj().T @ P)
+            P = P - W @ (W.conj().T @ P)
+            P = P - S @ (S.conj().T @ P)
+            P = orth(P)
+        # step 23: trial subspace
+        blocks = [V, W, S] + ([P] if P is not None else [])
+        Z = np.hstack(blocks)
+        # step 24: test subspace, projected first, then orthonormalised
+        Qh = C @ Z[:, b:]
+        Qh = Qh - Q @ (Q.conj().T @ Qh)
+        Qh = orth(Qh)
+        U = np.hstack([Q, Qh])
+        # step 25: harmonic Schur-Rayleigh-Ritz
+        F = U.conj().T @ (A @ Z)
+        Gm = U.conj().T @ Bx(Z)
+        RAb, RBb, YLb, YRb = ordqz(F, Gm, sigma)
+        # step 26
+        YR = YRb[:, :b]
+        YL = YLb[:, :b]
+        RA = RAb[:b, :b]
+        RB = RBb[:b, :b]
+        # steps 27-28: V = Z Y_R (= V Y_V + W Y_W + S Y_S + P Y_P), Q = U Y_L
+        V = Z @ YR
+        Q = U @ YL
+        # step 29: thick restart
+        P = Z @ YRb[:, b:2 * b] if p_mode == "thick" else None
+        # steps 30-31
+        MA, MB, _ = q_free_factors(RA, RB)
+        if keep_trace:
+            trace.append(dict(Z=Z, U=U, F=F, G=Gm, RAb=RAb, RBb=RBb, YLb=YLb, YRb=YRb,
+                              V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB))
+
+    return GplhrResult(V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB, lam=lam, X=X, rho=rho,
+                       iterations=it, converged=bool(np.max(rho[:k]) <= tol),
+                       history=history, lam_history=lam_history, trace=trace)
+
+
+def solve_problem(problem, tol: Optional[float] = None, maxit: int = 500, **kw) -> GplhrResult:
+    """Run the oracle on a ``problems.Problem`` (inputs only; no method code
+    lives there)."""
+    A = problem.A.to_scipy()
+    B = None if problem.B is None else problem.B.to_scipy()
+    Bm = sp.identity(A.shape[0], format="csr") if B is None else B
+    C = (A - problem.sigma * Bm).tocsr()
+    T = make_preconditioner(C, problem.precond, problem.sweeps, problem.omega)
+    return gplhr(A, B, problem.sigma, problem.k, problem.V0, T,
+                 tol=problem.tol if tol is None else tol, maxit=maxit, **kw)
