@@ -1,0 +1,234 @@
+/*
+ * gplhr.h -- C ABI of the MI355X (gfx950) GPLHR eigensolver library.
+ *
+ * GPLHR: Generalized Preconditioned Locally Harmonic Residual method
+ * (Vecharynski, Yang, Xue, arXiv 1506.06829).  The library computes the k
+ * eigenvalues of a regular pencil (A, B), A x = lambda B x (eq. gevp, Section 1),
+ * that lie closest to a shift sigma, together with an orthonormal basis V of
+ * right generalized Schur vectors, the left basis Q and the triangular factors
+ * R_A, R_B of the partial generalized Schur form A V = Q R_A, B V = Q R_B
+ * (eq. gschur, Section 2.1).  The iteration is Algorithm 2 ("The GPLHR
+ * algorithm", Section 3.5) with the harmonic Schur-Rayleigh-Ritz extraction of
+ * Section 3.3 and the thick-restart block P of Section 3.4 (eq. P1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved (re, im) pairs of IEEE doubles
+ *   ("complex128") unless a signature says complex64 (pairs of floats).
+ * - Dense n-by-w blocks on the device are ROW-MAJOR with a leading dimension
+ *   (elements between consecutive rows) >= w.
+ * - Small matrices on the host (k-by-k) are COLUMN-MAJOR complex128.
+ * - Device pointers must come from hipMalloc (or a caching allocator on top
+ *   of it) on the device that is current when gplhr_create is called.
+ * - Every call returns a gplhr_status; nothing throws across the ABI.  A
+ *   negative status is an error; the message is available from
+ *   gplhr_last_error(handle) (or gplhr_last_error(NULL) for errors raised
+ *   before a handle exists).
+ * - A handle is not thread-safe; separate handles are independent.  All
+ *   device work of a handle runs on the stream given in gplhr_options.
+ */
+#ifndef GPLHR_H
+#define GPLHR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gplhr_ctx *gplhr_t;
+
+typedef enum {
+    GPLHR_OK = 0,
+    GPLHR_NOT_CONVERGED = 1,       /* status, not an error: results are readable */
+    GPLHR_ERR_ARG = -1,            /* invalid argument or malformed CSR          */
+    GPLHR_ERR_ALLOC = -2,          /* device or host allocation failed           */
+    GPLHR_ERR_HIP = -3,            /* a HIP runtime call failed                  */
+    GPLHR_ERR_BREAKDOWN = -4,      /* orthonormalisation could not be completed  */
+    GPLHR_ERR_SINGULAR_SHIFT = -5, /* sigma is (numerically) an eigenvalue:
+                                      A - sigma B or the projected pencil is
+                                      singular (Proposition 3.1 fails)          */
+    GPLHR_ERR_NUMERIC = -6,        /* NaN/Inf in inputs or iterates              */
+    GPLHR_ERR_NOT_SIMPLE = -7,     /* backward: y^H B x ~ 0, lambda not simple   */
+    GPLHR_ERR_STATE = -8           /* call not valid in the handle's state       */
+} gplhr_status;
+
+/* Square sparse matrix in CSR form, all arrays on the device.
+ * row_ptr: n+1 int32, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz.
+ * col_idx: nnz int32 in [0, n), strictly increasing within each row.
+ * val:     nnz complex128.
+ * The library copies what it needs during gplhr_create; the caller may free
+ * the arrays afterwards. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const void *val;
+} gplhr_csr;
+
+/* Preconditioner T ~ (A - sigma B)^{-1} (Section 4; the paper only asks T to
+ * approximate the inverse of the shifted operator).  C denotes A - sigma B. */
+enum {
+    GPLHR_PRECOND_NONE = 0,   /* T = I                                          */
+    GPLHR_PRECOND_DIAG = 1,   /* T = diag(C)^{-1}                               */
+    GPLHR_PRECOND_JACOBI = 2  /* `sweeps` damped Jacobi steps on C w = r from
+                                 w_0 = 0: w_{t+1} = w_t + omega diag(C)^{-1}(r - C w_t) */
+};
+typedef struct {
+    int kind;
+    int sweeps;    /* JACOBI only, >= 1 */
+    double omega;  /* JACOBI only, damping factor in (0, 2) */
+} gplhr_precond;
+
+enum { GPLHR_FP64 = 0, GPLHR_MIXED = 1 };
+enum { GPLHR_P_THICK = 0, GPLHR_P_NONE = 2 };
+
+typedef struct {
+    int precision;      /* GPLHR_FP64: every block in complex128.
+                           GPLHR_MIXED: sparse products, preconditioner and block
+                           updates in complex64 with FP32 accumulation; Gram
+                           matrices, Cholesky factors, the projected pencil and
+                           residual norms in FP64; once the complex64 phase has
+                           converged to switch_tol or stalls, the iteration
+                           continues in complex128 from the current V and P
+                           until tol is met.                                      */
+    double tol;         /* stop when every one of the k leading Rayleigh-Ritz
+                           pairs has ||A x - lambda B x|| / ||A x|| <= tol       */
+    int max_iter;       /* iteration budget of gplhr_iterate when its max_iter<=0 */
+    int arnoldi_m;      /* m of Algorithms 1-2: number of S blocks (>= 1)        */
+    int p_mode;         /* GPLHR_P_THICK (eq. P1, default) or GPLHR_P_NONE       */
+    const void *V0;     /* device n-by-block complex128 row-major (ld = block),
+                           or NULL: a seeded complex normal block               */
+    uint64_t seed;      /* seed of the NULL-V0 generator                         */
+    void *hip_stream;   /* hipStream_t; NULL = the null stream                   */
+    double switch_tol;  /* MIXED: residual at which the FP64 phase starts        */
+    int stall_window;   /* MIXED: also switch after this many iterations without
+                           a 10% improvement of the largest residual              */
+    int timing;         /* 1: time every kernel class with HIP events (adds a
+                           small overhead); read with gplhr_get_stats            */
+} gplhr_options;
+
+/* Fill *opt with defaults: FP64, tol 1e-10, max_iter 500, arnoldi_m 1, thick P,
+ * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0. */
+void gplhr_default_options(gplhr_options *opt);
+
+/* Set up the operator C = A - sigma B on the union sparsity pattern, its
+ * diagonal, the preconditioner and all device workspace, then run the
+ * initialisation of Algorithm 2 (steps 1-4: V = orth(V0), Q = orth(C V),
+ * ordered QZ of (Q^H A V, Q^H B V), rotation of V and Q, M_A and M_B of
+ * eq. M with G1, G2 of eqs. G1_fix, G2_fix).
+ *
+ * A      n-by-n CSR (device).
+ * B      NULL for the standard problem B = I; otherwise n-by-n CSR (device).
+ *        A B with exactly one stored entry per row on the diagonal is kept as
+ *        a diagonal; any other B is applied as a sparse matrix.
+ * sigma  shift sigma_re + i sigma_im; must not be an eigenvalue (Algorithm 2
+ *        input; see also the caution that follows it).
+ * k      number of wanted eigenpairs, 1 <= k <= block.
+ * block  block width b of V, W, S_l, P (the paper uses b = k); the trial and
+ *        test bases have s = (arnoldi_m + 3) b columns and s must not exceed n.
+ * T      preconditioner (see gplhr_precond); NULL means GPLHR_PRECOND_NONE.
+ * opt    NULL for defaults.
+ * out    receives the handle (NULL on error).
+ * Errors: ARG (sizes, malformed CSR, bad options), NUMERIC (non-finite
+ * values), SINGULAR_SHIFT (zero on diag(C) with a diagonal-based T, or a
+ * singular projected pencil), ALLOC, HIP. */
+gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B,
+                          double sigma_re, double sigma_im, int k, int block,
+                          const gplhr_precond *T, const gplhr_options *opt,
+                          gplhr_t *out);
+
+/* Run GPLHR iterations (Algorithm 2, steps 5-31) until the convergence test
+ * of gplhr_options.tol holds or max_iter iterations have run (max_iter <= 0:
+ * use opt.max_iter).  n_converged (may be NULL) receives the number of leading
+ * pairs that meet tol; max_rel_resid (may be NULL) the largest relative
+ * residual over the k leading pairs.  Returns OK when converged,
+ * NOT_CONVERGED when the budget ran out; may be called again to continue. */
+gplhr_status gplhr_iterate(gplhr_t h, int max_iter, int *n_converged,
+                           double *max_rel_resid);
+
+/* Copy out the partial generalized Schur form (Algorithm 2 output).
+ * V, Q    device n-by-k complex128, row-major, ld = k (either may be NULL).
+ * RA, RB  host k-by-k complex128 column-major (either may be NULL).  For the
+ *         standard problem RA receives R = M_B^{-1} M_A and RB the identity.
+ * lambda  host k complex128: Rayleigh-Ritz eigenvalues on span(V), nearest
+ *         sigma first (may be NULL).
+ * rel_resid host k doubles: ||A x_j - lambda_j B x_j|| / ||A x_j|| (may be NULL).
+ * Synchronises the handle's stream. */
+gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB,
+                             double *lambda, double *rel_resid);
+
+/* Copy the unit-norm Rayleigh-Ritz eigenvectors x_j = V z_j (device n-by-k
+ * complex128 row-major, ld = k), in the order of gplhr_get_schur's lambda. */
+gplhr_status gplhr_get_eigvecs(gplhr_t h, void *X);
+
+/* Gradient of a real loss L(lambda_1..lambda_k) with respect to the stored
+ * values of A and B.  grad_lambda (host, k complex128) holds
+ * dL/dRe(lambda_j) + i dL/dIm(lambda_j).  The left eigenvectors y_j come from
+ * a GPLHR run on the adjoint pencil (A^H, B^H, conj(sigma)) with the same
+ * options; for a simple eigenvalue, d lambda = (y^H dA x - lambda y^H dB x) /
+ * (y^H B x), so each stored entry (i, j) receives
+ *   grad_valA[p] = sum_e g_e y_e[i] conj(x_e[j]) / conj(y_e^H B x_e) and
+ *   grad_valB[p] = -sum_e g_e conj(lambda_e) y_e[i] conj(x_e[j]) / conj(y_e^H B x_e)
+ * (device, nnz(A) and nnz(B) complex128, overwritten; grad_valB may be NULL
+ * and is ignored for B = I).  Requires a converged handle (STATE otherwise);
+ * NOT_SIMPLE when |y^H B x| <= 1e-12 ||y|| ||B x||. */
+gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda,
+                                void *grad_valA, void *grad_valB);
+
+/* Counters and timers of a handle. */
+typedef struct {
+    int64_t iterations;        /* GPLHR iterations since create             */
+    int64_t fp64_iterations;   /* of which in complex128                    */
+    int64_t spmm_calls;        /* sparse-times-block launches               */
+    int64_t precond_calls;     /* applications of T to a block              */
+    int64_t breakdowns;        /* orthonormalisations that needed a shift   */
+    double spmm_ms;            /* summed event time of SpMM launches (timing)*/
+    double spmm_bytes;         /* algorithmic bytes of those launches        */
+    double gram_ms;            /* Gram/reduction kernels (timing)           */
+    double update_ms;          /* block update kernels (timing)             */
+    double small_host_ms;      /* host projected-pencil step (wall clock)   */
+    double setup_ms;           /* gplhr_create wall clock                   */
+    double iterate_ms;         /* wall clock inside gplhr_iterate           */
+    double max_rel_resid;      /* last convergence check                    */
+    int n_converged;
+    int phase;                 /* 0 = complex64 phase, 1 = complex128        */
+} gplhr_stats;
+
+gplhr_status gplhr_get_stats(gplhr_t h, gplhr_stats *out);
+
+/* Release the handle and all workspace it owns.  NULL is a no-op. */
+void gplhr_destroy(gplhr_t h);
+
+/* Message of the last error on h (or of the last failed create when h is
+ * NULL).  Valid until the next call on the same handle. */
+const char *gplhr_last_error(gplhr_t h);
+
+/* ---------------------------------------------------------------------------
+ * Single-kernel entry points (the building blocks of the iteration, exported
+ * so that each can be checked and timed on its own).
+ * ------------------------------------------------------------------------ */
+
+/* Y = M X for a CSR matrix M and a dense row-major block X (sparse matrix
+ * times block, the "matblock" product the paper relies on, Section 3.5 and
+ * the remarks that follow Algorithm 2).  All pointers are device pointers.
+ * val, X, Y are complex128 (dtype 0) or complex64 (dtype 1, FP32
+ * accumulation).  X has ldx >= b, Y has ldy >= b, Y must not overlap X.
+ * col_idx and val may be NULL only when every row is empty.
+ * Returns ARG for b < 1 or b > 64 or bad leading dimensions. */
+gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr,
+                        const int32_t *col_idx, const void *val, const void *X,
+                        int ldx, void *Y, int ldy, int b, void *hip_stream);
+
+/* G = X^H Y in complex128 (FP64 accumulation, deterministic order) for
+ * row-major X (n-by-bx, ldx) and Y (n-by-by, ldy) of dtype 0 (complex128) or
+ * 1 (complex64).  G is a device bx-by-by complex128 array, column-major.
+ * 1 <= bx, by <= 64. */
+gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
+                        const void *Y, int ldy, int by, void *G, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPLHR_H */

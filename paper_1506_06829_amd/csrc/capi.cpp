@@ -1,0 +1,342 @@
+// C ABI of the GPLHR library (declarations and contracts in include/gplhr.h).
+// Every entry point converts internal exceptions to a gplhr_status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "driver.h"
+
+struct gplhr_ctx {
+    gplhr::Ctx c;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+gplhr_status guard(gplhr_t h, F &&f) {
+    try {
+        return static_cast<gplhr_status>(f());
+    } catch (const gplhr::Error &e) {
+        if (h) h->c.err = e.what();
+        g_last_error = e.what();
+        return static_cast<gplhr_status>(e.status);
+    } catch (const std::bad_alloc &) {
+        if (h) h->c.err = "host allocation failed";
+        g_last_error = "host allocation failed";
+        return GPLHR_ERR_ALLOC;
+    } catch (const std::exception &e) {
+        if (h) h->c.err = e.what();
+        g_last_error = e.what();
+        return GPLHR_ERR_ARG;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void gplhr_default_options(gplhr_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = GPLHR_FP64;
+    opt->tol = 1e-10;
+    opt->max_iter = 500;
+    opt->arnoldi_m = 1;
+    opt->p_mode = GPLHR_P_THICK;
+    opt->V0 = nullptr;
+    opt->seed = 1;
+    opt->hip_stream = nullptr;
+    opt->switch_tol = 1e-5;
+    opt->stall_window = 20;
+    opt->timing = 0;
+}
+
+gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B, double sigma_re,
+                          double sigma_im, int k, int block, const gplhr_precond *T,
+                          const gplhr_options *opt, gplhr_t *out) {
+    if (!out) {
+        g_last_error = "out must not be NULL";
+        return GPLHR_ERR_ARG;
+    }
+    *out = nullptr;
+    gplhr_t h = nullptr;
+    try {
+        h = new gplhr_ctx();
+    } catch (...) {
+        g_last_error = "host allocation failed";
+        return GPLHR_ERR_ALLOC;
+    }
+    gplhr_status s = guard(h, [&]() {
+        h->c.setup(A, B, gplhr::cd(sigma_re, sigma_im), k, block, T, opt);
+        return 0;
+    });
+    if (s < 0) {
+        g_last_error = h->c.err;
+        delete h;
+        return s;
+    }
+    *out = h;
+    return GPLHR_OK;
+}
+
+gplhr_status gplhr_iterate(gplhr_t h, int max_iter, int *n_converged, double *max_rel_resid) {
+    if (!h) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        const int s = h->c.run(max_iter);
+        if (n_converged) *n_converged = h->c.nconv;
+        if (max_rel_resid) *max_rel_resid = h->c.max_rho;
+        return s;
+    });
+}
+
+gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB, double *lambda,
+                             double *rel_resid) {
+    if (!h) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        gplhr::Ctx &c = h->c;
+        if ((int)c.lam_h.size() < c.k || (int)c.rho_h.size() < c.k || c.MB.r < c.k)
+            throw gplhr::Error(-8, "no iterate available");
+        c.copy_out(V, Q);
+        const int k = c.k;
+        using gplhr::small::Mat;
+        Mat ra(k, k), rb(k, k);
+        if (c.bk == gplhr::B_IDENT) {
+            // R = M_B^{-1} M_A (last line of Algorithm 2)
+            Mat mb(k, k), ma(k, k);
+            for (int j = 0; j < k; ++j)
+                for (int i = 0; i < k; ++i) {
+                    mb(i, j) = c.MB(i, j);
+                    ma(i, j) = c.MA(i, j);
+                }
+            Mat r;
+            if (!gplhr::small::lu_solve(mb, ma, r)) throw gplhr::Error(-6, "M_B is singular");
+            ra = r;
+            rb = Mat::eye(k);
+        } else {
+            for (int j = 0; j < k; ++j)
+                for (int i = 0; i < k; ++i) {
+                    ra(i, j) = c.RA(i, j);
+                    rb(i, j) = c.RB(i, j);
+                }
+        }
+        if (RA) std::memcpy(RA, ra.data(), sizeof(gplhr::cd) * k * k);
+        if (RB) std::memcpy(RB, rb.data(), sizeof(gplhr::cd) * k * k);
+        if (lambda) std::memcpy(lambda, c.lam_h.data(), sizeof(gplhr::cd) * k);
+        if (rel_resid) std::memcpy(rel_resid, c.rho_h.data(), sizeof(double) * k);
+        return c.converged ? 0 : 1;
+    });
+}
+
+gplhr_status gplhr_get_eigvecs(gplhr_t h, void *X) {
+    if (!h || !X) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        h->c.eigvecs(static_cast<double2 *>(X));
+        return 0;
+    });
+}
+
+gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad_valA,
+                                void *grad_valB) {
+    if (!h || !grad_lambda || !grad_valA) return GPLHR_ERR_ARG;
+    return guard(h, [&]() -> int {
+        gplhr::Ctx &c = h->c;
+        if (!c.converged) throw gplhr::Error(-8, "gplhr_eig_backward needs a converged handle");
+        const int64_t n = c.n;
+        const int k = c.k;
+        hipStream_t st = c.st;
+        // right eigenvectors x_e (unit norm)
+        double2 *X = nullptr, *Y = nullptr, *BX = nullptr, *coef = nullptr;
+        int32_t *trp = nullptr, *tci = nullptr, *brp = nullptr, *bci = nullptr;
+        double2 *tval = nullptr, *bval = nullptr;
+        struct Cleanup {
+            std::vector<void *> p;
+            ~Cleanup() {
+                for (void *q : p)
+                    if (q) (void)hipFree(q);
+            }
+        } cl;
+        GPLHR_HIP_CHECK(hipMalloc((void **)&X, sizeof(double2) * n * k));
+        cl.p.push_back(X);
+        c.eigvecs(X);
+        // left eigenvectors from the adjoint pencil (A^H, B^H, conj(sigma))
+        gplhr::csr_conj_transpose(st, n, c.a_nnz, c.a_rp, c.a_ci, c.a_val, &trp, &tci, &tval);
+        cl.p.push_back(trp); cl.p.push_back(tci); cl.p.push_back(tval);
+        gplhr_csr AH{n, c.a_nnz, trp, tci, tval};
+        gplhr_csr BH{};
+        const gplhr_csr *pBH = nullptr;
+        if (c.bk != gplhr::B_IDENT) {
+            gplhr::csr_conj_transpose(st, n, c.b_nnz, c.b_rp, c.b_ci, c.b_val, &brp, &bci, &bval);
+            cl.p.push_back(brp); cl.p.push_back(bci); cl.p.push_back(bval);
+            BH = gplhr_csr{n, c.b_nnz, brp, bci, bval};
+            pBH = &BH;
+        }
+        gplhr_options o2 = c.opt;
+        o2.V0 = nullptr;
+        o2.seed = c.opt.seed + 0x5bd1e995ULL;
+        gplhr::Ctx adj;
+        adj.setup(&AH, pBH, std::conj(c.sigma), k, c.b, &c.pre, &o2);
+        const int as = adj.run(c.opt.max_iter);
+        if (as != 0)
+            throw gplhr::Error(1, "adjoint solve did not converge (max residual " +
+                                      std::to_string(adj.max_rho) + ")");
+        GPLHR_HIP_CHECK(hipMalloc((void **)&Y, sizeof(double2) * n * k));
+        cl.p.push_back(Y);
+        adj.eigvecs(Y);
+        // pair each lambda_e with the adjoint eigenvalue nearest conj(lambda_e)
+        std::vector<int> perm(k, -1);
+        std::vector<bool> used(k, false);
+        for (int e = 0; e < k; ++e) {
+            double best = INFINITY;
+            int bj = -1;
+            for (int j = 0; j < k; ++j) {
+                if (used[j]) continue;
+                const double d = std::abs(adj.lam_h[j] - std::conj(c.lam_h[e]));
+                if (d < best) { best = d; bj = j; }
+            }
+            perm[e] = bj;
+            used[bj] = true;
+        }
+        {
+            std::vector<double2> P(k * k, make_double2(0.0, 0.0));
+            for (int e = 0; e < k; ++e) P[perm[e] + e * k] = make_double2(1.0, 0.0);
+            GPLHR_HIP_CHECK(hipMemcpy(c.coefY, P.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice));
+            gplhr::UpdTerm<double2> t;
+            t.in = Y; t.ld = k; t.col = 0; t.w = k; t.M = c.coefY; t.ldm = k;
+            gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+        }
+        // y_e^H B x_e and ||B x_e||
+        const double2 *bx = X;
+        const double2 *bsc = nullptr;
+        if (c.bk == gplhr::B_DIAG) {
+            bsc = c.bd;
+        } else if (c.bk == gplhr::B_SPARSE) {
+            GPLHR_HIP_CHECK(hipMalloc((void **)&BX, sizeof(double2) * n * k));
+            cl.p.push_back(BX);
+            gplhr::launch_spmm<double2>(st, n, c.b_rp, c.b_ci, c.b_val, X, k, BX, k, k, 0, nullptr, 0,
+                                        nullptr, false);
+            bx = BX;
+        }
+        c.gram<double2>(Y, k, k, bx, k, k, bsc, c.g0);
+        if (bsc) {
+            GPLHR_HIP_CHECK(hipMalloc((void **)&BX, sizeof(double2) * n * k));
+            cl.p.push_back(BX);
+            gplhr::launch_scale_rows<double2>(st, n, k, X, k, bsc, BX, k);
+            bx = BX;
+        }
+        c.gram<double2>(bx, k, k, bx, k, k, nullptr, c.g1);
+        std::vector<gplhr::cd> yBx(k * k), bxn(k * k);
+        GPLHR_HIP_CHECK(hipMemcpyAsync(yBx.data(), c.g0, sizeof(double2) * k * k, hipMemcpyDeviceToHost, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(bxn.data(), c.g1, sizeof(double2) * k * k, hipMemcpyDeviceToHost, st));
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        std::vector<gplhr::cd> ca(k), cb(k);
+        for (int e = 0; e < k; ++e) {
+            const gplhr::cd d = yBx[e + e * k];
+            const double nb = std::sqrt(std::abs(bxn[e + e * k].real()));
+            if (!(std::abs(d) > 1e-12 * nb))
+                throw gplhr::Error(-7, "eigenvalue " + std::to_string(e) + " is not simple (y^H B x ~ 0)");
+            const gplhr::cd g(grad_lambda[2 * e], grad_lambda[2 * e + 1]);
+            ca[e] = g / std::conj(d);
+            cb[e] = -ca[e] * std::conj(c.lam_h[e]);
+        }
+        GPLHR_HIP_CHECK(hipMalloc((void **)&coef, sizeof(double2) * 2 * k));
+        cl.p.push_back(coef);
+        GPLHR_HIP_CHECK(hipMemcpy(coef, ca.data(), sizeof(double2) * k, hipMemcpyHostToDevice));
+        GPLHR_HIP_CHECK(hipMemcpy(coef + k, cb.data(), sizeof(double2) * k, hipMemcpyHostToDevice));
+        gplhr::launch_sddmm(st, n, c.a_rp, c.a_ci, k, Y, k, X, k, coef,
+                            static_cast<double2 *>(grad_valA));
+        if (grad_valB && c.bk != gplhr::B_IDENT)
+            gplhr::launch_sddmm(st, n, c.b_rp, c.b_ci, k, Y, k, X, k, coef + k,
+                                static_cast<double2 *>(grad_valB));
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        return 0;
+    });
+}
+
+gplhr_status gplhr_get_stats(gplhr_t h, gplhr_stats *out) {
+    if (!h || !out) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        gplhr::Ctx &c = h->c;
+        std::memset(out, 0, sizeof(*out));
+        out->iterations = c.n_iter;
+        out->fp64_iterations = c.n_iter64;
+        out->spmm_calls = c.n_spmm;
+        out->precond_calls = c.n_prec;
+        out->breakdowns = c.n_breakdown;
+        auto ms = [&](int cls) {
+            auto it = c.timers.find(cls);
+            return it == c.timers.end() ? 0.0 : it->second.ms;
+        };
+        out->spmm_ms = ms(gplhr::T_SPMM);
+        out->spmm_bytes = c.spmm_bytes;
+        out->gram_ms = ms(gplhr::T_GRAM);
+        out->update_ms = ms(gplhr::T_UPDATE);
+        out->small_host_ms = c.small_ms;
+        out->setup_ms = c.setup_ms;
+        out->iterate_ms = c.iterate_ms;
+        out->max_rel_resid = c.max_rho;
+        out->n_converged = c.nconv;
+        out->phase = c.phase;
+        return 0;
+    });
+}
+
+void gplhr_destroy(gplhr_t h) { delete h; }
+
+const char *gplhr_last_error(gplhr_t h) {
+    if (h) return h->c.err.c_str();
+    return g_last_error.c_str();
+}
+
+gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        const void *val, const void *X, int ldx, void *Y, int ldy, int b,
+                        void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 0 || b < 1 || b > 64 || ldx < b || ldy < b || (dtype != 0 && dtype != 1))
+            throw gplhr::Error(-1, "gplhr_spmm: bad arguments");
+        if (n == 0) return 0;
+        if (!row_ptr || !X || !Y) throw gplhr::Error(-1, "gplhr_spmm: null pointer");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        if (dtype == 0)
+            gplhr::launch_spmm<double2>(st, n, row_ptr, col_idx, static_cast<const double2 *>(val),
+                                        static_cast<const double2 *>(X), ldx,
+                                        static_cast<double2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
+                                        true);
+        else
+            gplhr::launch_spmm<float2>(st, n, row_ptr, col_idx, static_cast<const float2 *>(val),
+                                       static_cast<const float2 *>(X), ldx,
+                                       static_cast<float2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
+                                       true);
+        return 0;
+    });
+}
+
+gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, const void *Y,
+                        int ldy, int by, void *G, void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 1 || bx < 1 || by < 1 || bx > 64 || by > 64 || ldx < bx || ldy < by ||
+            (dtype != 0 && dtype != 1) || !X || !Y || !G)
+            throw gplhr::Error(-1, "gplhr_gram: bad arguments");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int maxb = 512;
+        double2 *part = nullptr;
+        GPLHR_HIP_CHECK(hipMallocAsync((void **)&part, sizeof(double2) * maxb * bx * by, st));
+        int nblk;
+        if (dtype == 0)
+            nblk = gplhr::launch_gram_partials<double2>(st, n, static_cast<const double2 *>(X), ldx,
+                                                        bx, static_cast<const double2 *>(Y), ldy,
+                                                        by, nullptr, part, maxb);
+        else
+            nblk = gplhr::launch_gram_partials<float2>(st, n, static_cast<const float2 *>(X), ldx,
+                                                       bx, static_cast<const float2 *>(Y), ldy, by,
+                                                       nullptr, part, maxb);
+        gplhr::launch_reduce_partials(st, part, nblk, bx, by, static_cast<double2 *>(G), bx);
+        GPLHR_HIP_CHECK(hipFreeAsync(part, st));
+        return 0;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// GPLHR solver context (one per handle).
+#pragma once
+#include <complex>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "../../include/gplhr.h"
+#include "internal.h"
+#include "small_dense.h"
+
+namespace gplhr {
+
+using cd = std::complex<double>;
+
+enum BKind { B_IDENT = 0, B_DIAG = 1, B_SPARSE = 2 };
+
+// Per-precision operator views and block workspace.
+template <typename T>
+struct Work {
+    const T *cval = nullptr;   // values of C = A - sigma B
+    const T *bval = nullptr;   // values of a sparse B
+    const T *bd = nullptr;     // diagonal of a diagonal B
+    const T *dinv = nullptr;   // 1 / diag(C)
+    const T *dw = nullptr;     // omega / diag(C)
+    T *Z = nullptr, *CZ = nullptr, *BZ = nullptr, *U = nullptr;   // n x smax
+    T *R = nullptr, *J1 = nullptr, *J2 = nullptr;                  // n x b
+};
+
+struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    int used = 0;
+    double ms = 0.0;
+    int64_t count = 0;
+};
+
+enum { T_SPMM = 0, T_GRAM = 1, T_UPDATE = 2 };
+
+struct Ctx {
+    static constexpr int PART_BLOCKS = 512;
+    static constexpr int EYE_N = 64;
+    static constexpr int REFRESH_EVERY = 20;
+
+    std::string err;
+    hipStream_t st = nullptr;
+    gplhr_options opt{};
+    gplhr_precond pre{};
+    int64_t n = 0;
+    int k = 0, b = 0, m = 1, smax = 0;
+    cd sigma;
+    BKind bk = B_IDENT;
+    bool mixed = false, xcd_remap = true;
+    int phase = 1;
+    bool haveP = false, converged = false, checked = false;
+
+    // operator
+    int32_t *c_rp = nullptr, *c_ci = nullptr;
+    double2 *c_val = nullptr;
+    float2 *c_val32 = nullptr;
+    int64_t c_nnz = 0;
+    int32_t *a_rp = nullptr, *a_ci = nullptr;
+    double2 *a_val = nullptr;
+    int64_t a_nnz = 0;
+    int32_t *b_rp = nullptr, *b_ci = nullptr;
+    double2 *b_val = nullptr;
+    float2 *b_val32 = nullptr;
+    int64_t b_nnz = 0;
+    double2 *bd = nullptr, *dinv = nullptr, *dw = nullptr;
+    float2 *bd32 = nullptr, *dinv32 = nullptr, *dw32 = nullptr;
+
+    Work<double2> wd;
+    Work<float2> wf;
+
+    // small device buffers (FP64 complex)
+    double2 *part = nullptr, *g0 = nullptr, *g1 = nullptr, *rinv = nullptr, *eye = nullptr;
+    double2 *coefY = nullptr, *coefL = nullptr, *M1 = nullptr, *M2 = nullptr;
+    double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
+    double2 *xvec = nullptr;
+    int *dstatus = nullptr;
+    double2 *hpin = nullptr;   // pinned host staging
+
+    // host state of the iteration
+    small::Mat MA, MB, RA, RB, Zr_h;
+    std::vector<cd> lam_h;
+    std::vector<double> rho_h, resid_h, history;
+    double max_rho = INFINITY;
+    int nconv = 0;
+
+    // counters
+    int64_t n_iter = 0, n_iter64 = 0, n_spmm = 0, n_prec = 0, n_breakdown = 0;
+    double spmm_bytes = 0.0, small_ms = 0.0, setup_ms = 0.0, iterate_ms = 0.0;
+    std::map<int, Timer> timers;
+
+    ~Ctx();
+    void setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
+               const gplhr_precond *T, const gplhr_options *o);
+    int run(int max_it);
+    void switch_to_fp64();
+    void copy_out(void *V, void *Q);
+    void eigvecs(double2 *X);
+
+    void tbegin(int cls);
+    void tend(int cls);
+    void tflush();
+
+    template <typename T> Work<T> &W();
+    template <typename T>
+    void gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
+              double2 *out);
+    template <typename T>
+    void update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1, int nterms,
+                const UpdTerm<T> *terms);
+    template <typename T>
+    void project(T *X, int ldx, int xcol, int wx, const T *Y, int ldy, int ycol, int wy,
+                 T *mir1 = nullptr, const T *ymir1 = nullptr, T *mir2 = nullptr,
+                 const T *ymir2 = nullptr);
+    template <typename T>
+    void cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2);
+    template <typename T>
+    void spmm_c(const T *X, int ldx, T *Y, int ldy, int mode, const T *Rhs, int ldr);
+    template <typename T>
+    void spmm_b(const T *X, int ldx, T *Y, int ldy);
+    template <typename T> void apply_T(T *dest, int ldd, int dcol);
+    template <typename T> void srr_and_update(int s_cur, int nkeep_req);
+    template <typename T> void init_from_Z(int w0);
+    template <typename T> void iterate_once();
+    template <typename T> void refresh_products();
+    template <typename T> void check();
+};
+
+}  // namespace gplhr

@@ -1,0 +1,675 @@
+// GPLHR driver: Algorithm 2 ("The GPLHR algorithm", Section 3.5) on one HIP
+// stream, with the block work in kernels.hip and the small projected step in
+// small_dense.cpp.  Exposed through the C ABI in capi.cpp.
+//
+// Trial basis layout (n-by-smax, row-major, ld = smax, s = (m+3) b):
+//   Z = [ V | W | S_1 .. S_m | P ]   with V at column 0, W at b, S_l at (l+1) b,
+//   P at (m+2) b.  CZ = C Z with C = A - sigma B is kept alongside Z (fresh
+//   sparse products for W and S_l, the same linear combinations as Z for V and
+//   P), BZ likewise when B is a general sparse matrix.  U = [ Q | Qhat ].
+#include "driver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace gplhr {
+
+using small::Mat;
+
+static double2 to_d2(cd z) { return make_double2(z.real(), z.imag()); }
+
+// ---------------------------------------------------------------------------
+// allocation helpers
+// ---------------------------------------------------------------------------
+template <typename P>
+static void dalloc(P **p, size_t count) {
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&q, count * sizeof(P));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(-2, "device allocation of " + std::to_string(count * sizeof(P)) +
+                            " bytes failed: " + hipGetErrorString(e));
+    }
+    *p = static_cast<P *>(q);
+}
+template <typename P>
+static void dfree(P *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+Ctx::~Ctx() {
+    for (auto &pr : timers) {
+        for (auto &ev : pr.second.pool) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    }
+    dfree(c_rp); dfree(c_ci); dfree(c_val); dfree(c_val32);
+    dfree(a_rp); dfree(a_ci); dfree(a_val);
+    dfree(b_rp); dfree(b_ci); dfree(b_val); dfree(b_val32);
+    dfree(bd); dfree(bd32); dfree(dinv); dfree(dinv32); dfree(dw); dfree(dw32);
+    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); }
+    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); }
+    dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(eye); dfree(coefY); dfree(coefL);
+    dfree(M1); dfree(M2); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
+    dfree(dstatus); dfree(xvec);
+    if (hpin) (void)hipHostFree(hpin);
+}
+
+// ---------------------------------------------------------------------------
+// timing of kernel classes with HIP events on the solver stream
+// ---------------------------------------------------------------------------
+void Ctx::tbegin(int cls) {
+    if (!opt.timing) return;
+    Timer &t = timers[cls];
+    if (t.used == (int)t.pool.size()) {
+        hipEvent_t a, b;
+        GPLHR_HIP_CHECK(hipEventCreate(&a));
+        GPLHR_HIP_CHECK(hipEventCreate(&b));
+        t.pool.push_back({a, b});
+    }
+    GPLHR_HIP_CHECK(hipEventRecord(t.pool[t.used].first, st));
+}
+void Ctx::tend(int cls) {
+    if (!opt.timing) return;
+    Timer &t = timers[cls];
+    GPLHR_HIP_CHECK(hipEventRecord(t.pool[t.used].second, st));
+    ++t.used;
+}
+void Ctx::tflush() {
+    if (!opt.timing) return;
+    for (auto &pr : timers) {
+        Timer &t = pr.second;
+        for (int i = 0; i < t.used; ++i) {
+            float ms = 0.f;
+            GPLHR_HIP_CHECK(hipEventSynchronize(t.pool[i].second));
+            GPLHR_HIP_CHECK(hipEventElapsedTime(&ms, t.pool[i].first, t.pool[i].second));
+            t.ms += ms;
+            t.count += 1;
+        }
+        t.used = 0;
+    }
+}
+
+template <> Work<double2> &Ctx::W<double2>() { return wd; }
+template <> Work<float2> &Ctx::W<float2>() { return wf; }
+
+// ---------------------------------------------------------------------------
+// block primitives
+// ---------------------------------------------------------------------------
+template <typename T>
+void Ctx::gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
+               double2 *out) {
+    tbegin(T_GRAM);
+    const int nblk = launch_gram_partials<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_BLOCKS);
+    launch_reduce_partials(st, part, nblk, bx, by, out, bx);
+    tend(T_GRAM);
+}
+
+template <typename T>
+void Ctx::update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1,
+                 int nterms, const UpdTerm<T> *terms) {
+    tbegin(T_UPDATE);
+    launch_update<T>(st, n, out, ldo, wout, ocol, split, ocol2,
+                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms);
+    tend(T_UPDATE);
+}
+
+// X(:, xcol:xcol+wx) -= Y(:, ycol:ycol+wy) (Y^H X)   [mirrors receive the same
+// coefficients applied to their own columns]
+template <typename T>
+void Ctx::project(T *X, int ldx, int xcol, int wx, const T *Y, int ldy, int ycol, int wy,
+                  T *mir1, const T *ymir1, T *mir2, const T *ymir2) {
+    gram<T>(Y + ycol, ldy, wy, X + xcol, ldx, wx, nullptr, g0);
+    UpdTerm<T> t;
+    t.in = Y; t.ld = ldy; t.col = ycol; t.w = wy; t.M = g0; t.ldm = wy;
+    t.alpha = make_double2(-1.0, 0.0);
+    update<T>(X, ldx, wx, xcol, wx, 0, true, 1, &t);
+    if (mir1) {
+        t.in = ymir1;
+        update<T>(mir1, ldx, wx, xcol, wx, 0, true, 1, &t);
+    }
+    if (mir2) {
+        t.in = ymir2;
+        update<T>(mir2, ldx, wx, xcol, wx, 0, true, 1, &t);
+    }
+}
+
+// Cholesky-QR, `passes` times: X <- X R^{-1} with X^H X = R^H R (FP64 Gram);
+// mirrors are multiplied by the same R^{-1}.
+template <typename T>
+void Ctx::cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2) {
+    for (int p = 0; p < passes; ++p) {
+        gram<T>(X + col, ld, w, X + col, ld, w, nullptr, g0);
+        launch_chol_rinv(st, w, g0, rinv, dstatus);
+        UpdTerm<T> t;
+        t.in = X; t.ld = ld; t.col = col; t.w = w; t.M = rinv; t.ldm = w;
+        update<T>(X, ld, w, col, w, 0, false, 1, &t);
+        if (mir1) {
+            t.in = mir1;
+            update<T>(mir1, ld, w, col, w, 0, false, 1, &t);
+        }
+        if (mir2) {
+            t.in = mir2;
+            update<T>(mir2, ld, w, col, w, 0, false, 1, &t);
+        }
+    }
+}
+
+template <typename T>
+void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int mode, const T *Rhs, int ldr) {
+    Work<T> &w = W<T>();
+    tbegin(T_SPMM);
+    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, b, mode, Rhs, ldr, w.dw, xcd_remap);
+    tend(T_SPMM);
+    ++n_spmm;
+    spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
+                  (double)n * b * sizeof(T) * (mode == 0 ? 2 : 3);
+}
+
+template <typename T>
+void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy) {
+    Work<T> &w = W<T>();
+    tbegin(T_SPMM);
+    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, b, 0, nullptr, 0, nullptr, xcd_remap);
+    tend(T_SPMM);
+    ++n_spmm;
+    spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * b * sizeof(T);
+}
+
+// dest(:, dcol:dcol+b) = T R  (R = Work.R, ld b)
+template <typename T>
+void Ctx::apply_T(T *dest, int ldd, int dcol) {
+    Work<T> &w = W<T>();
+    ++n_prec;
+    if (pre.kind == GPLHR_PRECOND_NONE) {
+        launch_scale_rows<T>(st, n, b, w.R, b, nullptr, dest + dcol, ldd);
+    } else if (pre.kind == GPLHR_PRECOND_DIAG) {
+        launch_scale_rows<T>(st, n, b, w.R, b, w.dinv, dest + dcol, ldd);
+    } else {
+        // w_1 = omega D^{-1} r; w_{t+1} = w_t + omega D^{-1} (r - C w_t)
+        if (pre.sweeps == 1) {
+            launch_scale_rows<T>(st, n, b, w.R, b, w.dw, dest + dcol, ldd);
+            return;
+        }
+        launch_scale_rows<T>(st, n, b, w.R, b, w.dw, w.J1, b);
+        T *cur = w.J1;
+        for (int t = 1; t < pre.sweeps; ++t) {
+            const bool last = (t == pre.sweeps - 1);
+            T *o = last ? dest + dcol : (cur == w.J1 ? w.J2 : w.J1);
+            spmm_c<T>(cur, b, o, last ? ldd : b, 1, w.R, b);
+            cur = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// projected pencil -> ordered Schur form -> basis update
+// ---------------------------------------------------------------------------
+template <typename T>
+void Ctx::srr_and_update(int s_cur, int nkeep_req) {
+    Work<T> &w = W<T>();
+    const int ld = smax;
+    const T *bsrc = (bk == B_SPARSE) ? w.BZ : w.Z;
+    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+    // a8: F1 = U^H (A - sigma B) Z, F2 = U^H B Z   (s_cur x s_cur, FP64)
+    gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
+    gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
+    const size_t ss = (size_t)s_cur * s_cur;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, F1, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + ss, F2, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + 2 * ss, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    tflush();
+    {
+        int stv = 0;
+        std::memcpy(&stv, hpin + 2 * ss, sizeof(int));
+        n_breakdown = stv;
+    }
+    // a9: ordered generalized Schur form on the host (FP64)
+    auto t0 = std::chrono::steady_clock::now();
+    Mat K(s_cur, s_cur), Gm(s_cur, s_cur);
+    std::memcpy(K.data(), hpin, ss * sizeof(cd));
+    std::memcpy(Gm.data(), hpin + ss, ss * sizeof(cd));
+    for (const cd &v : K.a)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+            throw Error(-6, "non-finite entries in the projected pencil");
+    const int nkeep = std::min(nkeep_req, s_cur);
+    small::SrrResult r;
+    if (!small::harmonic_srr(K, Gm, sigma, b, nkeep, r))
+        throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
+                        "(Proposition 3.1)");
+    small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    RA = r.RA; RB = r.RB; MA = r.MA; MB = r.MB;
+    // coefficients: [Y_R | Y_P] (s_cur x ncols), Y_L (s_cur x b), M1 = M_B, M2 = sigma M_B - M_A
+    const int nc = r.ncols;
+    size_t off = 0;
+    std::memcpy(hpin + off, r.YR.data(), (size_t)s_cur * nc * sizeof(cd));
+    off += (size_t)s_cur * nc;
+    std::memcpy(hpin + off, r.YL.data(), (size_t)s_cur * b * sizeof(cd));
+    off += (size_t)s_cur * b;
+    Mat m2(b, b);
+    for (int j = 0; j < b; ++j)
+        for (int i = 0; i < b; ++i) m2(i, j) = sigma * MB(i, j) - MA(i, j);
+    std::memcpy(hpin + off, MB.data(), (size_t)b * b * sizeof(cd));
+    off += (size_t)b * b;
+    std::memcpy(hpin + off, m2.data(), (size_t)b * b * sizeof(cd));
+    off += (size_t)b * b;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(coefY, hpin, (size_t)s_cur * nc * sizeof(double2), hipMemcpyHostToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(coefL, hpin + (size_t)s_cur * nc, (size_t)s_cur * b * sizeof(double2), hipMemcpyHostToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(M1, hpin + (size_t)s_cur * (nc + b), (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(M2, hpin + (size_t)s_cur * (nc + b) + (size_t)b * b, (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
+    // a10: V = Z Y_R, P = Z Ybar_R(:, b+1:2b) (and the same for CZ, BZ); Q = U Y_L
+    const int offP = (m + 2) * b;
+    UpdTerm<T> t;
+    t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
+    t.in = w.Z;
+    update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
+    t.in = w.CZ;
+    update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
+    if (bk == B_SPARSE) {
+        t.in = w.BZ;
+        update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
+    }
+    t.in = w.U; t.M = coefL;
+    update<T>(w.U, ld, b, 0, b, 0, false, 1, &t);
+    // The host writes the pinned staging buffer again only after a stream
+    // synchronisation, so the uploads above cannot be overtaken.
+    haveP = (nc >= 2 * b);
+}
+
+// Steps 1-4 of Algorithm 2 from Z(:, 0:w0) (V0, or [V P] when restarting in
+// another precision): orthonormalise, C Z, U = orth(C Z), ordered QZ, rotate.
+template <typename T>
+void Ctx::init_from_Z(int w0) {
+    Work<T> &w = W<T>();
+    const int ld = smax;
+    cholqr<T>(w.Z, ld, 0, w0, 2, nullptr, nullptr);
+    for (int c = 0; c < w0; c += b) {
+        spmm_c<T>(w.Z + c, ld, w.CZ + c, ld, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(w.Z + c, ld, w.BZ + c, ld);
+    }
+    launch_scale_rows<T>(st, n, w0, w.CZ, ld, nullptr, w.U, ld);
+    cholqr<T>(w.U, ld, 0, w0, 2, nullptr, nullptr);
+    const int nkeep = (w0 >= 2 * b && opt.p_mode == GPLHR_P_THICK) ? 2 * b : b;
+    srr_and_update<T>(w0, nkeep);
+}
+
+// One GPLHR iteration (Algorithm 2, steps 6-31).
+template <typename T>
+void Ctx::iterate_once() {
+    Work<T> &w = W<T>();
+    const int ld = smax;
+    const int offW = b, offP = (m + 2) * b;
+    const int s_cur = haveP ? smax : (m + 2) * b;
+    T *Z = w.Z, *CZ = w.CZ, *BZ = w.BZ, *U = w.U;
+    // left projector basis: Q when B != I, V when B = I (steps 8/10, 15/17)
+    const T *Lb = (bk == B_IDENT) ? Z : U;
+    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+
+    // src block -> new block at dst:
+    //   R = (A - sigma B) X M_B + B X (sigma M_B - M_A)  (= A X M_B - B X M_A)
+    //   R <- (I - Q Q^H) R;  Y = T R;  Y <- (I - [V W S_<l] [.]^H) Y (two passes)
+    //   Y <- orth(Y);  C Y (and B Y)
+    auto build = [&](int src, int dst) {
+        UpdTerm<T> t[2];
+        t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = b; t[0].M = M1; t[0].ldm = b;
+        t[1].in = (bk == B_SPARSE) ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = b;
+        t[1].M = M2; t[1].ldm = b; t[1].rowscale = bsc;
+        update<T>(w.R, b, b, 0, b, 0, false, 2, t);
+        project<T>(w.R, b, 0, b, Lb, ld, 0, b);
+        apply_T<T>(Z, ld, dst);
+        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, dst, b, Z, ld, 0, dst);
+        cholqr<T>(Z, ld, dst, b, 2, nullptr, nullptr);
+        spmm_c<T>(Z + dst, ld, CZ + dst, ld, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(Z + dst, ld, BZ + dst, ld);
+    };
+    build(0, offW);                                   // W (steps 6-12)
+    for (int l = 1; l <= m; ++l) build(offW + (l - 1) * b, offW + l * b);   // S_l (steps 13-21)
+
+    // step 22: P <- orth(P - [V W S][V W S]^H P), mirrored onto C P (and B P)
+    if (haveP) {
+        for (int pass = 0; pass < 2; ++pass)
+            project<T>(Z, ld, offP, b, Z, ld, 0, offP, CZ, CZ, bk == B_SPARSE ? BZ : nullptr,
+                       bk == B_SPARSE ? BZ : nullptr);
+        cholqr<T>(Z, ld, offP, b, 2, CZ, bk == B_SPARSE ? BZ : nullptr);
+    }
+    // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])]
+    const int wq = s_cur - b;
+    gram<T>(U, ld, b, CZ + b, ld, wq, nullptr, g0);
+    {
+        UpdTerm<T> t[2];
+        t[0].in = CZ; t[0].ld = ld; t[0].col = b; t[0].w = wq; t[0].M = eye; t[0].ldm = EYE_N;
+        t[1].in = U; t[1].ld = ld; t[1].col = 0; t[1].w = b; t[1].M = g0; t[1].ldm = b;
+        t[1].alpha = make_double2(-1.0, 0.0);
+        update<T>(U, ld, wq, b, wq, 0, false, 2, t);
+    }
+    project<T>(U, ld, b, wq, U, ld, 0, b);
+    cholqr<T>(U, ld, b, wq, 2, nullptr, nullptr);
+    // steps 25-31
+    srr_and_update<T>(s_cur, opt.p_mode == GPLHR_P_THICK ? 2 * b : b);
+    ++n_iter;
+    if (sizeof(T) == sizeof(double2)) ++n_iter64;
+}
+
+// Exact C V, C P (and B V, B P) by fresh sparse products: removes the drift of
+// the mirrored products.
+template <typename T>
+void Ctx::refresh_products() {
+    Work<T> &w = W<T>();
+    const int ld = smax, offP = (m + 2) * b;
+    spmm_c<T>(w.Z, ld, w.CZ, ld, 0, nullptr, 0);
+    if (bk == B_SPARSE) spmm_b<T>(w.Z, ld, w.BZ, ld);
+    if (haveP) {
+        spmm_c<T>(w.Z + offP, ld, w.CZ + offP, ld, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(w.Z + offP, ld, w.BZ + offP, ld);
+    }
+}
+
+// Rayleigh-Ritz pairs on span(V) and their relative residuals (FP64).
+template <typename T>
+void Ctx::check() {
+    Work<T> &w = W<T>();
+    const int ld = smax;
+    const T *bsrc = (bk == B_SPARSE) ? w.BZ : w.Z;
+    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+    gram<T>(w.Z, ld, b, w.CZ, ld, b, nullptr, g0);
+    gram<T>(w.Z, ld, b, bsrc, ld, b, bsc, g1);
+    const size_t bb = (size_t)b * b;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, g0, bb * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb, g1, bb * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    Mat Va(b, b), Vb(b, b);
+    std::memcpy(Va.data(), hpin, bb * sizeof(cd));
+    std::memcpy(Vb.data(), hpin + bb, bb * sizeof(cd));
+    for (size_t e = 0; e < bb; ++e) {
+        Va.a[e] += sigma * Vb.a[e];
+        if (!std::isfinite(Va.a[e].real()) || !std::isfinite(Va.a[e].imag()) ||
+            !std::isfinite(Vb.a[e].real()) || !std::isfinite(Vb.a[e].imag()))
+            throw Error(-6, "non-finite Rayleigh quotient matrices");
+    }
+    std::vector<cd> lam;
+    Mat Zr;
+    if (!small::ritz(Va, Vb, sigma, lam, Zr)) throw Error(-6, "Rayleigh-Ritz step failed");
+    lam_h = lam;
+    Zr_h = Zr;
+    std::memcpy(hpin, Zr.data(), bb * sizeof(cd));
+    std::memcpy(hpin + bb, lam.data(), b * sizeof(cd));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(dZr, hpin, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(dlam, hpin + bb, b * sizeof(double2), hipMemcpyHostToDevice, st));
+    const int nblk = launch_resid_partials<T>(st, n, b, w.CZ, ld, w.Z, ld,
+                                              bk == B_SPARSE ? w.BZ : nullptr, ld, bsc,
+                                              to_d2(sigma), dZr, dlam, part, PART_BLOCKS);
+    launch_reduce_partials(st, part, nblk, b, 1, rnorm, b);
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb + b, rnorm, b * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    rho_h.assign(b, 0.0);
+    resid_h.assign(b, 0.0);
+    max_rho = 0.0;
+    nconv = 0;
+    bool lead = true;
+    for (int j = 0; j < b; ++j) {
+        const cd v = reinterpret_cast<cd *>(hpin)[bb + b + j];
+        resid_h[j] = std::sqrt(v.real());
+        rho_h[j] = v.imag() > 0 ? std::sqrt(v.real() / v.imag()) : INFINITY;
+        if (!std::isfinite(rho_h[j]) && v.imag() > 0) throw Error(-6, "non-finite residual");
+        if (j < k) {
+            max_rho = std::max(max_rho, rho_h[j]);
+            if (lead && rho_h[j] <= opt.tol) ++nconv;
+            else lead = false;
+        }
+    }
+    history.push_back(max_rho);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
+                const gplhr_precond *T, const gplhr_options *o) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (o) opt = *o; else gplhr_default_options(&opt);
+    if (T) pre = *T; else { pre.kind = GPLHR_PRECOND_NONE; pre.sweeps = 0; pre.omega = 0.0; }
+    st = static_cast<hipStream_t>(opt.hip_stream);
+    sigma = sig;
+    if (!A || !A->row_ptr || !A->col_idx || !A->val) throw Error(-1, "A must be a device CSR");
+    n = A->n;
+    k = k_;
+    b = b_;
+    m = opt.arnoldi_m;
+    if (n < 1 || n > INT32_MAX - 1) throw Error(-1, "n out of range");
+    if (A->nnz < 0 || A->nnz > INT32_MAX) throw Error(-1, "nnz(A) out of range");
+    if (k < 1 || b < k) throw Error(-1, "need 1 <= k <= block");
+    if (m < 1) throw Error(-1, "arnoldi_m must be >= 1");
+    if (opt.p_mode != GPLHR_P_THICK && opt.p_mode != GPLHR_P_NONE) throw Error(-1, "unsupported p_mode");
+    if (opt.precision != GPLHR_FP64 && opt.precision != GPLHR_MIXED) throw Error(-1, "bad precision");
+    smax = (m + 3) * b;
+    if ((m + 2) * b > 48 || smax > 64)
+        throw Error(-1, "(m+2)*block must be <= 48 and (m+3)*block <= 64");
+    if (smax > n) throw Error(-1, "trial subspace (m+3)*block exceeds n");
+    if (!(opt.tol >= 0.0)) throw Error(-1, "tol must be >= 0");
+    if (pre.kind == GPLHR_PRECOND_JACOBI && (pre.sweeps < 1 || !(pre.omega > 0.0 && pre.omega < 2.0)))
+        throw Error(-1, "Jacobi needs sweeps >= 1 and 0 < omega < 2");
+    if (pre.kind < 0 || pre.kind > 2) throw Error(-1, "unknown preconditioner");
+    if (!std::isfinite(sigma.real()) || !std::isfinite(sigma.imag())) throw Error(-1, "sigma must be finite");
+
+    // A: validate and keep a copy (pattern + values) for the backward pass
+    int32_t ends[2];
+    GPLHR_HIP_CHECK(hipMemcpy(&ends[0], A->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+    GPLHR_HIP_CHECK(hipMemcpy(&ends[1], A->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (ends[0] != 0 || ends[1] != A->nnz) throw Error(-1, "A: row_ptr[0] must be 0 and row_ptr[n] = nnz");
+    int64_t bad_rows = 0, bad_vals = 0;
+    csr_validate(st, n, A->row_ptr, A->col_idx, static_cast<const double2 *>(A->val), &bad_rows, &bad_vals);
+    if (bad_rows) throw Error(-1, "A: " + std::to_string(bad_rows) + " rows with unsorted, duplicate or out-of-range columns");
+    if (bad_vals) throw Error(-6, "A: non-finite values");
+    a_nnz = A->nnz;
+    dalloc(&a_rp, n + 1); dalloc(&a_ci, a_nnz); dalloc(&a_val, a_nnz);
+    GPLHR_HIP_CHECK(hipMemcpyAsync(a_rp, A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(a_ci, A->col_idx, sizeof(int32_t) * a_nnz, hipMemcpyDeviceToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(a_val, A->val, sizeof(double2) * a_nnz, hipMemcpyDeviceToDevice, st));
+
+    bk = B_IDENT;
+    if (B) {
+        if (!B->row_ptr || !B->col_idx || !B->val) throw Error(-1, "B must be a device CSR");
+        if (B->n != n) throw Error(-1, "A and B must have the same order");
+        if (B->nnz < 0 || B->nnz > INT32_MAX) throw Error(-1, "nnz(B) out of range");
+        GPLHR_HIP_CHECK(hipMemcpy(&ends[0], B->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+        GPLHR_HIP_CHECK(hipMemcpy(&ends[1], B->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (ends[0] != 0 || ends[1] != B->nnz) throw Error(-1, "B: row_ptr[0] must be 0 and row_ptr[n] = nnz");
+        csr_validate(st, n, B->row_ptr, B->col_idx, static_cast<const double2 *>(B->val), &bad_rows, &bad_vals);
+        if (bad_rows) throw Error(-1, "B: " + std::to_string(bad_rows) + " malformed rows");
+        if (bad_vals) throw Error(-6, "B: non-finite values");
+        b_nnz = B->nnz;
+        dalloc(&b_rp, n + 1); dalloc(&b_ci, b_nnz); dalloc(&b_val, b_nnz);
+        GPLHR_HIP_CHECK(hipMemcpyAsync(b_rp, B->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(b_ci, B->col_idx, sizeof(int32_t) * b_nnz, hipMemcpyDeviceToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(b_val, B->val, sizeof(double2) * b_nnz, hipMemcpyDeviceToDevice, st));
+        const int64_t nondiag = csr_count_nondiag_rows(st, n, b_rp, b_ci);
+        if (nondiag == 0) {
+            bk = B_DIAG;
+            dalloc(&bd, n);
+            GPLHR_HIP_CHECK(hipMemcpyAsync(bd, b_val, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        } else {
+            bk = B_SPARSE;
+        }
+    }
+    // a1: C = A - sigma B on the union pattern, its diagonal, the preconditioner
+    c_nnz = build_shifted(st, n, a_rp, a_ci, a_val, bk == B_IDENT ? 0 : 1, b_rp, b_ci, b_val,
+                          to_d2(sigma), &c_rp, &c_ci, &c_val);
+    if (pre.kind != GPLHR_PRECOND_NONE) {
+        double2 *dg = nullptr;
+        dalloc(&dg, n);
+        const int64_t zeros = extract_diag(st, n, c_rp, c_ci, c_val, dg);
+        if (zeros) {
+            dfree(dg);
+            throw Error(-5, "diag(A - sigma B) has " + std::to_string(zeros) + " zero entries");
+        }
+        dalloc(&dinv, n);
+        launch_recip_scaled(st, n, dg, make_double2(1.0, 0.0), dinv);
+        if (pre.kind == GPLHR_PRECOND_JACOBI) {
+            dalloc(&dw, n);
+            launch_recip_scaled(st, n, dg, make_double2(pre.omega, 0.0), dw);
+        }
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        dfree(dg);
+    }
+    mixed = (opt.precision == GPLHR_MIXED);
+    phase = mixed ? 0 : 1;
+
+    // workspace
+    const size_t blk_s = (size_t)n * smax, blk_b = (size_t)n * b;
+    wd.cval = c_val; wd.bval = b_val; wd.bd = bd; wd.dinv = dinv; wd.dw = dw;
+    dalloc(&wd.Z, blk_s); dalloc(&wd.CZ, blk_s); dalloc(&wd.U, blk_s);
+    if (bk == B_SPARSE) dalloc(&wd.BZ, blk_s);
+    dalloc(&wd.R, blk_b);
+    if (pre.kind == GPLHR_PRECOND_JACOBI && pre.sweeps > 1) { dalloc(&wd.J1, blk_b); dalloc(&wd.J2, blk_b); }
+    if (mixed) {
+        dalloc(&c_val32, c_nnz);
+        launch_c128_to_c64_flat(st, c_nnz, c_val, c_val32);
+        wf.cval = c_val32;
+        if (bk == B_SPARSE) { dalloc(&b_val32, b_nnz); launch_c128_to_c64_flat(st, b_nnz, b_val, b_val32); wf.bval = b_val32; }
+        if (bk == B_DIAG) { dalloc(&bd32, n); launch_c128_to_c64_flat(st, n, bd, bd32); wf.bd = bd32; }
+        if (dinv) { dalloc(&dinv32, n); launch_c128_to_c64_flat(st, n, dinv, dinv32); wf.dinv = dinv32; }
+        if (dw) { dalloc(&dw32, n); launch_c128_to_c64_flat(st, n, dw, dw32); wf.dw = dw32; }
+        dalloc(&wf.Z, blk_s); dalloc(&wf.CZ, blk_s); dalloc(&wf.U, blk_s);
+        if (bk == B_SPARSE) dalloc(&wf.BZ, blk_s);
+        dalloc(&wf.R, blk_b);
+        if (pre.kind == GPLHR_PRECOND_JACOBI && pre.sweeps > 1) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
+    }
+    dalloc(&part, (size_t)PART_BLOCKS * 64 * 64);
+    dalloc(&g0, 64 * 64); dalloc(&g1, 64 * 64); dalloc(&rinv, 64 * 64);
+    dalloc(&eye, EYE_N * EYE_N); dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
+    dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
+    dalloc(&dZr, 64 * 64); dalloc(&dlam, 64); dalloc(&rnorm, 64); dalloc(&dstatus, 1);
+    GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
+    {
+        std::vector<double2> e(EYE_N * EYE_N, make_double2(0.0, 0.0));
+        for (int i = 0; i < EYE_N; ++i) e[i + i * EYE_N] = make_double2(1.0, 0.0);
+        GPLHR_HIP_CHECK(hipMemcpy(eye, e.data(), e.size() * sizeof(double2), hipMemcpyHostToDevice));
+    }
+    GPLHR_HIP_CHECK(hipHostMalloc((void **)&hpin, sizeof(double2) * 4 * 64 * 64 + 4096, hipHostMallocDefault));
+
+    // V0 -> Z(:, 0:b), then steps 1-4
+    if (opt.V0)
+        GPLHR_HIP_CHECK(hipMemcpy2DAsync(wd.Z, smax * sizeof(double2), opt.V0, b * sizeof(double2),
+                                         b * sizeof(double2), n, hipMemcpyDeviceToDevice, st));
+    else
+        launch_randn(st, n, b, opt.seed, wd.Z, smax);
+    if (mixed) {
+        launch_c128_to_c64(st, n, b, wd.Z, smax, wf.Z, smax);
+        init_from_Z<float2>(b);
+    } else {
+        init_from_Z<double2>(b);
+    }
+    if (phase == 0) check<float2>(); else check<double2>();
+    checked = true;
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void Ctx::switch_to_fp64() {
+    const int offP = (m + 2) * b;
+    launch_c64_to_c128(st, n, b, wf.Z, smax, wd.Z, smax);
+    int w0 = b;
+    if (haveP) {
+        launch_c64_to_c128(st, n, b, wf.Z + offP, smax, wd.Z + b, smax);
+        w0 = 2 * b;
+    }
+    phase = 1;
+    init_from_Z<double2>(w0);
+    checked = false;
+}
+
+int Ctx::run(int max_it) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (max_it <= 0) max_it = opt.max_iter;
+    int status = 1;
+    int done = 0;
+    double best = INFINITY;
+    int since_best = 0;
+    int since_refresh = 0;
+    while (true) {
+        if (!checked) {
+            if (phase == 0) check<float2>(); else check<double2>();
+            checked = true;
+        }
+        if (phase == 1 && max_rho <= opt.tol) {
+            // confirm with freshly computed sparse products
+            refresh_products<double2>();
+            check<double2>();
+            since_refresh = 0;
+            if (max_rho <= opt.tol) { status = 0; converged = true; break; }
+        }
+        if (phase == 0) {
+            if (max_rho < 0.9 * best) { best = max_rho; since_best = 0; }
+            else ++since_best;
+            if (max_rho <= opt.switch_tol || since_best >= opt.stall_window) {
+                switch_to_fp64();
+                continue;
+            }
+        }
+        if (done >= max_it) break;
+        if (phase == 0) iterate_once<float2>(); else iterate_once<double2>();
+        checked = false;
+        ++done;
+        if (phase == 1 && ++since_refresh >= REFRESH_EVERY) {
+            refresh_products<double2>();
+            since_refresh = 0;
+            checked = false;
+        }
+    }
+    tflush();
+    iterate_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+// V, Q (n x k, ld k) in complex128
+void Ctx::copy_out(void *V, void *Q) {
+    if (phase == 0) {
+        if (V) launch_c64_to_c128(st, n, k, wf.Z, smax, static_cast<double2 *>(V), k);
+        if (Q) launch_c64_to_c128(st, n, k, wf.U, smax, static_cast<double2 *>(Q), k);
+    } else {
+        if (V) GPLHR_HIP_CHECK(hipMemcpy2DAsync(V, k * sizeof(double2), wd.Z, smax * sizeof(double2), k * sizeof(double2), n, hipMemcpyDeviceToDevice, st));
+        if (Q) GPLHR_HIP_CHECK(hipMemcpy2DAsync(Q, k * sizeof(double2), wd.U, smax * sizeof(double2), k * sizeof(double2), n, hipMemcpyDeviceToDevice, st));
+    }
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// x_j = V z_j, j < k (n x k, ld k, complex128)
+void Ctx::eigvecs(double2 *X) {
+    const size_t bb = (size_t)b * b;
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    std::memcpy(hpin, Zr_h.data(), bb * sizeof(cd));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(dZr, hpin, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+    UpdTerm<double2> t;
+    t.col = 0; t.w = b; t.M = dZr; t.ldm = b;
+    if (phase == 0) {
+        double2 *tmp = nullptr;
+        dalloc(&tmp, (size_t)n * b);
+        launch_c64_to_c128(st, n, b, wf.Z, smax, tmp, b);
+        t.in = tmp; t.ld = b;
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        dfree(tmp);
+    } else {
+        t.in = wd.Z; t.ld = smax;
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    }
+}
+
+// explicit instantiations
+template void Ctx::iterate_once<double2>();
+template void Ctx::iterate_once<float2>();
+
+}  // namespace gplhr
+namespace gplhr {
+template void Ctx::gram<double2>(const double2 *, int, int, const double2 *, int, int,
+                                 const double2 *, double2 *);
+template void Ctx::gram<float2>(const float2 *, int, int, const float2 *, int, int, const float2 *,
+                                double2 *);
+}  // namespace gplhr

@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP kernels, the driver and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace gplhr {
+
+// Status carried by exceptions inside the library; converted to gplhr_status
+// at the C boundary.
+struct Error : std::runtime_error {
+    int status;
+    Error(int st, const std::string &msg) : std::runtime_error(msg), status(st) {}
+};
+
+#define GPLHR_HIP_CHECK(expr)                                                               \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::gplhr::Error(-3, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels.hip).  T is double2 (complex128) or float2
+// (complex64).  All blocks are row-major with explicit leading dimensions.
+// ---------------------------------------------------------------------------
+
+// Y = C X (mode 0) or, for the damped Jacobi sweep, Y = X + dw .* (Rhs - C X)
+// (mode 1), where dw holds omega / C(i,i) per row.
+template <typename T>
+void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, const T *val,
+                 const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
+                 const T *dw, bool xcd_remap);
+
+// partial Gram sums of X^H (diag(yscale) Y); yscale (complex per row) may be
+// null.  Writes nblk partial bx-by-by matrices into `part` (entry-major:
+// part[e * nblk + blk], e = p + q*bx) and returns nblk.
+template <typename T>
+int launch_gram_partials(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
+                         int ldy, int by, const T *yscale, double2 *part, int max_blocks);
+
+// out[e * ldo_stride...]: out is column-major with leading dimension ldo:
+// out[p + q*ldo] = sum_blk part[(p + q*bx) * nblk + blk]  (fixed order)
+void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,
+                            double2 *out, int ldo);
+
+// One term of a block update: alpha * diag(rowscale) * In(:, col:col+w) * M,
+// M column-major w-by-wout (leading dimension ldm), FP64 complex.
+template <typename T>
+struct UpdTerm {
+    const T *in = nullptr;
+    int ld = 0;
+    int col = 0;
+    int w = 0;
+    const double2 *M = nullptr;
+    int ldm = 0;
+    double2 alpha = {1.0, 0.0};
+    const T *rowscale = nullptr;
+};
+
+// Out(:, map(c)) = beta * Out(:, map(c)) + sum_t term_t(:, c), c < wout, with
+// map(c) = ocol + c for c < split and ocol2 + (c - split) otherwise.  Row-local,
+// so Out may alias any input (every row is staged before it is written).
+template <typename T>
+void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms);
+
+// Cholesky-QR factor: given the w-by-w Gram G (column-major, Hermitian),
+// writes Rinv (column-major, upper triangular) with X Rinv orthonormal for
+// X^H X = G.  Diagonal scaling first; a vanishing pivot triggers a diagonal
+// shift and increments status[0].
+void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status);
+
+// Out(:, 0:w) = rowscale .* In(:, 0:w)  (rowscale complex per row; null = copy)
+template <typename T>
+void launch_scale_rows(hipStream_t st, int64_t n, int w, const T *in, int ldi, const T *rowscale,
+                       T *out, int ldo);
+
+// Convert between precisions (w columns).
+void launch_c128_to_c64(hipStream_t st, int64_t n, int w, const double2 *in, int ldi, float2 *out,
+                        int ldo);
+void launch_c64_to_c128(hipStream_t st, int64_t n, int w, const float2 *in, int ldi, double2 *out,
+                        int ldo);
+void launch_c128_to_c64_flat(hipStream_t st, int64_t cnt, const double2 *in, float2 *out);
+
+// Residual partials for the Rayleigh-Ritz pairs (lambda_j, x_j = V z_j):
+//   ax = (CV + sigma BV) z_j, bx = BV z_j, r = ax - lambda_j bx,
+// accumulating (|r|^2, |ax|^2) per j in FP64.  BV is either an explicit block
+// (bv, ldb) or V scaled by bscale (complex per row; null = identity).
+template <typename T>
+int launch_resid_partials(hipStream_t st, int64_t n, int b, const T *CV, int ldc, const T *V,
+                          int ldv, const T *bv, int ldb, const T *bscale, double2 sigma,
+                          const double2 *Zr, const double2 *lam, double2 *part, int max_blocks);
+
+// Seeded complex normal block (counter-based hash + Box-Muller).
+void launch_randn(hipStream_t st, int64_t n, int w, uint64_t seed, double2 *out, int ldo);
+
+// --- setup --------------------------------------------------------------
+// Count malformed rows of a CSR (unsorted/duplicate/out-of-range columns or
+// decreasing row pointers) and non-finite values; returns (bad_rows, bad_vals).
+void csr_validate(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci,
+                  const double2 *val, int64_t *bad_rows, int64_t *bad_vals);
+// Number of rows that are not exactly one stored diagonal entry.
+int64_t csr_count_nondiag_rows(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci);
+
+// Union-pattern C = A - sigma B.  bkind: 0 identity, 1 sparse (rp/ci/val of
+// B).  Allocates rp/ci/val of C (device) and returns nnz(C).
+int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32_t *aci,
+                      const double2 *aval, int bkind, const int32_t *brp, const int32_t *bci,
+                      const double2 *bval, double2 sigma, int32_t **crp, int32_t **cci,
+                      double2 **cval);
+// d[i] = C(i,i) (0 when not stored); returns the number of zero diagonal entries.
+int64_t extract_diag(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci,
+                     const double2 *val, double2 *d);
+// out[i] = num / d[i]
+void launch_recip_scaled(hipStream_t st, int64_t n, const double2 *d, double2 num, double2 *out);
+// Conjugate transpose of a CSR (count / scan / scatter).  Allocates the result.
+void csr_conj_transpose(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp,
+                        const int32_t *ci, const double2 *val, int32_t **trp, int32_t **tci,
+                        double2 **tval);
+// grad[p] = sum_e coef_e * Y[i,e] * conj(X[j,e]) for each stored (i, j) = entry p.
+void launch_sddmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, int k,
+                  const double2 *Y, int ldy, const double2 *X, int ldx, const double2 *coef,
+                  double2 *grad);
+
+}  // namespace gplhr

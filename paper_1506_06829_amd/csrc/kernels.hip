@@ -1,0 +1,1095 @@
+// HIP kernels (gfx950) for the GPLHR block iteration: CSR sparse-times-block
+// products, FP64-accumulated Gram matrices with a deterministic two-level
+// reduction, row-local block updates staged through LDS, the Cholesky-QR
+// factor, residual norms and the one-time operator setup.
+//
+// Layout: every n-by-w block is row-major ("block-row interleaved"): row i of
+// a block is w contiguous complex values, so a sparse-row gather reads whole
+// contiguous segments and every reduction over n walks contiguous rows.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace gplhr {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc += a * b
+__device__ __forceinline__ void cfma(double2 &acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cfma(float2 &acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+__device__ __forceinline__ void cfma_cj(double2 &acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 to_d(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d(float2 a) { return make_double2((double)a.x, (double)a.y); }
+template <typename T> __device__ __forceinline__ T from_d(double2 a);
+template <> __device__ __forceinline__ double2 from_d<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from_d<float2>(double2 a) {
+    return make_float2((float)a.x, (float)a.y);
+}
+template <typename T> __device__ __forceinline__ T czero();
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+
+static inline int ceil_div_i(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// CSR sparse matrix times row-major block
+// ---------------------------------------------------------------------------
+// A group of `lpr` consecutive lanes owns one matrix row; lane l of the group
+// owns CPL consecutive columns of the block (CPL = 2 for complex64 so every
+// lane moves 16 bytes).  The row's index/value stream is read by all lanes of
+// the group at the same address (one broadcast transaction), the gathered
+// block rows are contiguous segments, and no cross-lane reduction is needed.
+template <typename T, int CPL>
+struct VecOf;
+template <> struct VecOf<double2, 1> { using V = double2; };
+template <> struct VecOf<float2, 1> { using V = float2; };
+template <> struct VecOf<float2, 2> { using V = float4; };
+
+template <typename T, int CPL>
+__device__ __forceinline__ void load_vec(const T *p, T (&x)[CPL]) {
+    if constexpr (CPL == 1) {
+        x[0] = *p;
+    } else {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        x[0] = make_float2(v.x, v.y);
+        x[1] = make_float2(v.z, v.w);
+    }
+}
+template <typename T, int CPL>
+__device__ __forceinline__ void store_vec(T *p, const T (&x)[CPL]) {
+    if constexpr (CPL == 1) {
+        *p = x[0];
+    } else {
+        *reinterpret_cast<float4 *>(p) = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+    }
+}
+
+template <typename T>
+struct SpmmArgs {
+    int64_t n;
+    const int32_t *rp;
+    const int32_t *ci;
+    const T *val;
+    const T *X;
+    int ldx;
+    T *Y;
+    int ldy;
+    int b;
+    int mode;
+    const T *Rhs;
+    int ldr;
+    const T *dw;
+    int lpr;        // lanes per row
+    int rpw;        // rows per wavefront
+    int nblocks;    // blocks that carry rows
+    int per_xcd;    // >0: XCD-contiguous block remap
+};
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
+    int blk = blockIdx.x;
+    if (a.per_xcd > 0) {
+        blk = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+        if (blk >= a.nblocks) return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rw = lane / a.lpr;
+    const int cl = lane - rw * a.lpr;
+    const int64_t row = ((int64_t)blk * 4 + wave) * a.rpw + rw;
+    const int c0 = cl * CPL;
+    if (rw >= a.rpw || row >= a.n || c0 >= a.b) return;
+
+    T acc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) acc[u] = czero<T>();
+    const int p0 = a.rp[row], p1 = a.rp[row + 1];
+    const T *__restrict__ Xc = a.X + c0;
+    int p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        int j[4];
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            j[u] = a.ci[p + u];
+            v[u] = a.val[p + u];
+        }
+        T x[4][CPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load_vec<T, CPL>(Xc + (int64_t)j[u] * a.ldx, x[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) cfma(acc[c], v[u], x[u][c]);
+    }
+    for (; p < p1; ++p) {
+        const int j = a.ci[p];
+        const T v = a.val[p];
+        T x[CPL];
+        load_vec<T, CPL>(Xc + (int64_t)j * a.ldx, x);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cfma(acc[c], v, x[c]);
+    }
+    T out[CPL];
+    if (a.mode == 0) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) out[c] = acc[c];
+    } else {
+        T xo[CPL], rh[CPL];
+        load_vec<T, CPL>(a.X + row * a.ldx + c0, xo);
+        load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
+        const T w = a.dw[row];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            out[c] = xo[c];
+            cfma(out[c], w, csub(rh[c], acc[c]));
+        }
+    }
+    store_vec<T, CPL>(a.Y + row * a.ldy + c0, out);
+}
+
+template <typename T>
+void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, const T *val,
+                 const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
+                 const T *dw, bool xcd_remap) {
+    if (n <= 0) return;
+    SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0};
+    bool two = false;
+    if constexpr (sizeof(T) == 8) {
+        two = (b % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) && (mode == 0 || ldr % 2 == 0) &&
+              ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16 == 0) &&
+              (mode == 0 || reinterpret_cast<uintptr_t>(Rhs) % 16 == 0);
+    }
+    const int cpl = two ? 2 : 1;
+    a.lpr = (b + cpl - 1) / cpl;
+    if (a.lpr > 64) throw Error(-1, "spmm: block too wide");
+    a.rpw = 64 / a.lpr;
+    const int64_t rows_per_block = 4LL * a.rpw;
+    const int nblocks = ceil_div_i(n, rows_per_block);
+    a.nblocks = nblocks;
+    int grid = nblocks;
+    if (xcd_remap && nblocks >= 64) {
+        grid = (nblocks + 7) / 8 * 8;
+        a.per_xcd = grid / 8;
+    }
+    if constexpr (sizeof(T) == 8) {
+        if (two)
+            hipLaunchKernelGGL((spmm_kernel<T, 2>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a);
+    }
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+template void launch_spmm<double2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
+                                   const double2 *, const double2 *, int, double2 *, int, int,
+                                   int, const double2 *, int, const double2 *, bool);
+template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
+                                  const float2 *, const float2 *, int, float2 *, int, int, int,
+                                  const float2 *, int, const float2 *, bool);
+
+// ---------------------------------------------------------------------------
+// Gram partials G_blk = X(rows_blk,:)^H diag(yscale) Y(rows_blk,:), FP64
+// ---------------------------------------------------------------------------
+// Threads form groups; each group covers the whole bx-by-by output with
+// RX-by-RY register tiles and walks a strided subset of the block's rows.
+// Groups are summed in LDS in a fixed order, so results are bitwise
+// reproducible run to run.
+template <typename T>
+struct GramArgs {
+    int64_t n;
+    const T *X;
+    int ldx;
+    int bx;
+    const T *Y;
+    int ldy;
+    int by;
+    const T *yscale;
+    double2 *part;
+    int nblk;
+    int64_t rows_per_blk;
+    int tx, ty;
+};
+
+template <typename T, int RX, int RY>
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a) {
+    extern __shared__ double2 sh_gram[];
+    const int tid = threadIdx.x;
+    const int nt = a.tx * a.ty;
+    const int groups = 256 / nt;
+    const int g = tid / nt;
+    const int t = tid - g * nt;
+    const int ti = t % a.tx, tj = t / a.tx;
+    const int p0 = ti * RX, q0 = tj * RY;
+    double2 acc[RX][RY];
+#pragma unroll
+    for (int i = 0; i < RX; ++i)
+#pragma unroll
+        for (int j = 0; j < RY; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_blk;
+    const int64_t r1 = min(a.n, r0 + a.rows_per_blk);
+    if (g < groups) {
+        for (int64_t r = r0 + g; r < r1; r += groups) {
+            double2 xv[RX], yv[RY];
+            const T *xr = a.X + r * a.ldx;
+            const T *yr = a.Y + r * a.ldy;
+#pragma unroll
+            for (int i = 0; i < RX; ++i)
+                xv[i] = (p0 + i < a.bx) ? to_d(xr[p0 + i]) : make_double2(0.0, 0.0);
+            double2 sc = make_double2(1.0, 0.0);
+            if (a.yscale) sc = to_d(a.yscale[r]);
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                double2 y = (q0 + j < a.by) ? to_d(yr[q0 + j]) : make_double2(0.0, 0.0);
+                yv[j] = a.yscale ? cmul(sc, y) : y;
+            }
+#pragma unroll
+            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                for (int j = 0; j < RY; ++j) cfma_cj(acc[i][j], xv[i], yv[j]);
+        }
+    }
+    const int nent = a.bx * a.by;
+    if (groups == 1) {
+#pragma unroll
+        for (int i = 0; i < RX; ++i)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                const int p = p0 + i, q = q0 + j;
+                if (g == 0 && p < a.bx && q < a.by)
+                    a.part[(int64_t)(p + q * a.bx) * a.nblk + blockIdx.x] = acc[i][j];
+            }
+        return;
+    }
+    for (int gg = 0; gg < groups; ++gg) {
+        if (g == gg) {
+#pragma unroll
+            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    const int p = p0 + i, q = q0 + j;
+                    if (p < a.bx && q < a.by) {
+                        const int e = p + q * a.bx;
+                        sh_gram[e] = (gg == 0) ? acc[i][j] : cadd(sh_gram[e], acc[i][j]);
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nent; e += 256) a.part[(int64_t)e * a.nblk + blockIdx.x] = sh_gram[e];
+}
+
+template <typename T>
+int launch_gram_partials(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
+                         int ldy, int by, const T *yscale, double2 *part, int max_blocks) {
+    if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
+    GramArgs<T> a{};
+    a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
+    a.yscale = yscale; a.part = part;
+    const bool big = (bx * by > 400);
+    const int RX = big ? 4 : 2, RY = big ? 4 : 2;
+    a.tx = (bx + RX - 1) / RX;
+    a.ty = (by + RY - 1) / RY;
+    if (a.tx * a.ty > 256) throw Error(-1, "gram: tile too large");
+    const int64_t min_rows = 128;
+    int nblk = (int)std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n + min_rows - 1) / min_rows));
+    a.nblk = nblk;
+    a.rows_per_blk = (n + nblk - 1) / nblk;
+    const int groups = 256 / (a.tx * a.ty);
+    const size_t shmem = groups > 1 ? sizeof(double2) * bx * by : 0;
+    if (big)
+        hipLaunchKernelGGL((gram_kernel<T, 4, 4>), dim3(nblk), dim3(256), shmem, st, a);
+    else
+        hipLaunchKernelGGL((gram_kernel<T, 2, 2>), dim3(nblk), dim3(256), shmem, st, a);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    return nblk;
+}
+template int launch_gram_partials<double2>(hipStream_t, int64_t, const double2 *, int, int,
+                                           const double2 *, int, int, const double2 *, double2 *,
+                                           int);
+template int launch_gram_partials<float2>(hipStream_t, int64_t, const float2 *, int, int,
+                                          const float2 *, int, int, const float2 *, double2 *,
+                                          int);
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double2 *part, int nblk,
+                                                              int bx, double2 *out, int ldo) {
+    __shared__ double2 sh[256];
+    const int e = blockIdx.x;
+    const double2 *src = part + (int64_t)e * nblk;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nblk; i += 256) acc = cadd(acc, src[i]);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int p = e % bx, q = e / bx;
+        out[p + (int64_t)q * ldo] = sh[0];
+    }
+}
+
+void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,
+                            double2 *out, int ldo) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(bx * by), dim3(256), 0, st, part, nblk, bx,
+                       out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// row-local block update through LDS
+// ---------------------------------------------------------------------------
+template <typename T>
+struct UpdArgs {
+    int64_t n;
+    T *out;
+    int ldo, wout, ocol, split, ocol2;
+    double2 beta;
+    int nterms;
+    UpdTerm<T> t[3];
+    int wtot;   // sum of term widths
+    int tr;     // rows per block
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
+    extern __shared__ double2 sh_upd_raw[];
+    T *sM = reinterpret_cast<T *>(sh_upd_raw);                 // wtot x wout
+    T *sIn = sM + (size_t)a.wtot * a.wout;                      // tr x (wtot+1)
+    const int ldi = a.wtot + 1;
+    const int tid = threadIdx.x;
+    // coefficients, alpha folded in
+    {
+        int base = 0;
+        for (int t = 0; t < a.nterms; ++t) {
+            const int w = a.t[t].w;
+            for (int e = tid; e < w * a.wout; e += 256) {
+                const int j = e % w, c = e / w;
+                const double2 m = a.t[t].M[j + (int64_t)c * a.t[t].ldm];
+                sM[(base + j) * a.wout + c] = from_d<T>(cmul(a.t[t].alpha, m));
+            }
+            base += w;
+        }
+    }
+    const int64_t row0 = (int64_t)blockIdx.x * a.tr;
+    const int rows = (int)min((int64_t)a.tr, a.n - row0);
+    {
+        int base = 0;
+        for (int t = 0; t < a.nterms; ++t) {
+            const int w = a.t[t].w;
+            const T *in = a.t[t].in;
+            const T *rs = a.t[t].rowscale;
+            for (int e = tid; e < rows * w; e += 256) {
+                const int r = e / w, j = e - r * w;
+                const int64_t gi = row0 + r;
+                T v = in[gi * a.t[t].ld + a.t[t].col + j];
+                if (rs) v = cmul(rs[gi], v);
+                sIn[r * ldi + base + j] = v;
+            }
+            base += w;
+        }
+    }
+    // old values of the output (beta != 0), read before any write
+    constexpr int MAXP = 8;
+    T old[MAXP];
+    const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
+    const int npairs = rows * a.wout;
+    int k = 0;
+    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
+        if (use_beta) {
+            const int r = e / a.wout, c = e - r * a.wout;
+            const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+            old[k] = a.out[(row0 + r) * a.ldo + oc];
+        }
+    }
+    __syncthreads();
+    T res[MAXP];
+    k = 0;
+    const T beta = from_d<T>(a.beta);
+    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
+        const int r = e / a.wout, c = e - r * a.wout;
+        T acc = czero<T>();
+        const T *xi = sIn + r * ldi;
+        for (int j = 0; j < a.wtot; ++j) cfma(acc, xi[j], sM[j * a.wout + c]);
+        if (use_beta) cfma(acc, beta, old[k]);
+        res[k] = acc;
+    }
+    k = 0;
+    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
+        const int r = e / a.wout, c = e - r * a.wout;
+        const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+        a.out[(row0 + r) * a.ldo + oc] = res[k];
+    }
+}
+
+template <typename T>
+void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms) {
+    if (n <= 0) return;
+    if (nterms < 0 || nterms > 3 || wout < 1 || wout > 64) throw Error(-1, "update: bad shape");
+    UpdArgs<T> a{};
+    a.n = n; a.out = out; a.ldo = ldo; a.wout = wout; a.ocol = ocol; a.split = split;
+    a.ocol2 = ocol2; a.beta = beta; a.nterms = nterms;
+    int wtot = 0;
+    for (int t = 0; t < nterms; ++t) {
+        a.t[t] = terms[t];
+        wtot += terms[t].w;
+    }
+    if (wtot < 1 || wtot > 128) throw Error(-1, "update: input too wide");
+    a.wtot = wtot;
+    const size_t esz = sizeof(T);
+    const size_t budget = 64 * 1024;
+    const size_t msz = (size_t)wtot * wout * esz;
+    size_t tr = (budget - msz) / ((size_t)(wtot + 1) * esz);
+    tr = std::min<size_t>(tr, 2048 / (size_t)wout);   // at most 8 outputs per thread
+    tr = std::min<size_t>(tr, 64);
+    if (tr < 1) throw Error(-1, "update: LDS budget exceeded");
+    a.tr = (int)tr;
+    const size_t shmem = msz + tr * (wtot + 1) * esz;
+    const int grid = ceil_div_i(n, (int64_t)tr);
+    hipLaunchKernelGGL((update_kernel<T>), dim3(grid), dim3(256), shmem, st, a);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
+                                     double2, int, const UpdTerm<double2> *);
+template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, int, int, int,
+                                    double2, int, const UpdTerm<float2> *);
+
+// ---------------------------------------------------------------------------
+// Cholesky-QR factor (one workgroup, w <= 64)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G, double2 *Rinv,
+                                                        int *status) {
+    // A holds the scaled Gram; its upper triangle becomes R (A = R^H R) and
+    // its strict lower triangle then receives R^{-1} transposed (the diagonal
+    // of R^{-1} goes to dinv).
+    __shared__ double2 A[48 * 48];
+    __shared__ double dsc[48];
+    __shared__ double dinv[48];
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    if (tid == 0) flag = 0;
+    for (int e = tid; e < w * w; e += 256) A[e] = G[e];
+    __syncthreads();
+    if (tid < w) {
+        const double g = A[tid + tid * w].x;
+        const bool ok = (g > 0.0) && isfinite(g);
+        dsc[tid] = ok ? 1.0 / sqrt(g) : 1.0;
+        if (!ok) atomicAdd(&flag, 1);
+    }
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e % w, j = e / w;
+        A[e].x *= dsc[i] * dsc[j];
+        A[e].y *= dsc[i] * dsc[j];
+    }
+    __syncthreads();
+    const double tol = 64.0 * 2.220446049250313e-16;
+    for (int j = 0; j < w; ++j) {
+        if (tid == 0) {
+            double piv = A[j + j * w].x;
+            if (!(piv > tol) || !isfinite(piv)) {
+                piv = tol;   // shifted factor; the second Cholesky-QR pass restores orthogonality
+                flag += 1;
+            }
+            A[j + j * w] = make_double2(sqrt(piv), 0.0);
+        }
+        __syncthreads();
+        const double rjj = A[j + j * w].x;
+        for (int c = j + 1 + tid; c < w; c += 256) {
+            A[j + c * w].x /= rjj;
+            A[j + c * w].y /= rjj;
+        }
+        __syncthreads();
+        const int m = w - j - 1;
+        for (int e = tid; e < m * m; e += 256) {
+            const int ii = j + 1 + e % m, cc = j + 1 + e / m;
+            if (ii <= cc) {
+                const double2 ri = A[j + ii * w], rc = A[j + cc * w];
+                double2 v = A[ii + cc * w];
+                v.x -= ri.x * rc.x + ri.y * rc.y;   // conj(ri) * rc
+                v.y -= ri.x * rc.y - ri.y * rc.x;
+                A[ii + cc * w] = v;
+            }
+        }
+        __syncthreads();
+    }
+    // R^{-1}, row by row from the bottom: Rinv(i,j) = (delta_ij - sum_{l=i+1..j}
+    // R(i,l) Rinv(l,j)) / R(i,i); Rinv(i,j) (i<j) is kept at A[j + i*w].
+    for (int i = w - 1; i >= 0; --i) {
+        const double rii = A[i + i * w].x;
+        for (int j = i + tid; j < w; j += 256) {
+            if (j == i) {
+                dinv[i] = 1.0 / rii;
+            } else {
+                double2 s = make_double2(0.0, 0.0);
+                for (int l = i + 1; l <= j; ++l) {
+                    const double2 r = A[i + l * w];
+                    const double2 x = (l == j) ? make_double2(dinv[j], 0.0) : A[j + l * w];
+                    s.x += r.x * x.x - r.y * x.y;
+                    s.y += r.x * x.y + r.y * x.x;
+                }
+                A[j + i * w] = make_double2(-s.x / rii, -s.y / rii);
+            }
+        }
+        __syncthreads();
+    }
+    // X Rinv with Rinv = D R_s^{-1}
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e % w, j = e / w;
+        double2 v = make_double2(0.0, 0.0);
+        if (i == j)
+            v = make_double2(dinv[i], 0.0);
+        else if (i < j)
+            v = A[j + i * w];
+        Rinv[e] = make_double2(v.x * dsc[i], v.y * dsc[i]);
+    }
+    __syncthreads();
+    if (tid == 0 && flag > 0 && status) atomicAdd(status, flag);
+}
+
+void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status) {
+    if (w < 1 || w > 48) throw Error(-1, "cholqr: width out of range");
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void scale_rows_kernel(int64_t n, int w, const T *in, int ldi, const T *rs, T *out,
+                                  int ldo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t i = e / w;
+    const int c = (int)(e - i * w);
+    T v = in[i * ldi + c];
+    if (rs) v = cmul(rs[i], v);
+    out[i * ldo + c] = v;
+}
+template <typename T>
+void launch_scale_rows(hipStream_t st, int64_t n, int w, const T *in, int ldi, const T *rowscale,
+                       T *out, int ldo) {
+    if (n <= 0) return;
+    const int64_t tot = n * w;
+    hipLaunchKernelGGL((scale_rows_kernel<T>), dim3(ceil_div_i(tot, 256)), dim3(256), 0, st, n, w,
+                       in, ldi, rowscale, out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+template void launch_scale_rows<double2>(hipStream_t, int64_t, int, const double2 *, int,
+                                         const double2 *, double2 *, int);
+template void launch_scale_rows<float2>(hipStream_t, int64_t, int, const float2 *, int,
+                                        const float2 *, float2 *, int);
+
+__global__ void c128_to_c64_kernel(int64_t n, int w, const double2 *in, int ldi, float2 *out,
+                                   int ldo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t i = e / w;
+    const int c = (int)(e - i * w);
+    const double2 v = in[i * ldi + c];
+    out[i * ldo + c] = make_float2((float)v.x, (float)v.y);
+}
+__global__ void c64_to_c128_kernel(int64_t n, int w, const float2 *in, int ldi, double2 *out,
+                                   int ldo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t i = e / w;
+    const int c = (int)(e - i * w);
+    const float2 v = in[i * ldi + c];
+    out[i * ldo + c] = make_double2((double)v.x, (double)v.y);
+}
+void launch_c128_to_c64(hipStream_t st, int64_t n, int w, const double2 *in, int ldi, float2 *out,
+                        int ldo) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(c128_to_c64_kernel, dim3(ceil_div_i(n * w, 256)), dim3(256), 0, st, n, w,
+                       in, ldi, out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+void launch_c64_to_c128(hipStream_t st, int64_t n, int w, const float2 *in, int ldi, double2 *out,
+                        int ldo) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(c64_to_c128_kernel, dim3(ceil_div_i(n * w, 256)), dim3(256), 0, st, n, w,
+                       in, ldi, out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+void launch_c128_to_c64_flat(hipStream_t st, int64_t cnt, const double2 *in, float2 *out) {
+    launch_c128_to_c64(st, cnt, 1, in, 1, out, 1);
+}
+
+// ---------------------------------------------------------------------------
+// residual norms of Rayleigh-Ritz pairs (FP64)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ResidArgs {
+    int64_t n;
+    int b;
+    const T *CV;
+    int ldc;
+    const T *V;
+    int ldv;
+    const T *bv;
+    int ldb;
+    const T *bscale;
+    double2 sigma;
+    const double2 *Zr;
+    const double2 *lam;
+    double2 *part;
+    int nblk;
+    int64_t rows_per_blk;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void resid_kernel(ResidArgs<T> a) {
+    __shared__ double2 sZ[32 * 32];
+    __shared__ double2 sl[32];
+    __shared__ double2 red[256];
+    const int b = a.b;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < b * b; e += 256) sZ[e] = a.Zr[e];
+    if (tid < b) sl[tid] = a.lam[tid];
+    __syncthreads();
+    const int rpt = 256 / b;        // rows handled concurrently
+    const int r_off = tid / b, j = tid - r_off * b;
+    double2 acc = make_double2(0.0, 0.0);
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_blk;
+    const int64_t r1 = min(a.n, r0 + a.rows_per_blk);
+    if (r_off < rpt) {
+        for (int64_t r = r0 + r_off; r < r1; r += rpt) {
+            double2 ax = make_double2(0.0, 0.0), bx = make_double2(0.0, 0.0);
+            const double2 sc = a.bscale ? to_d(a.bscale[r]) : make_double2(1.0, 0.0);
+            for (int c = 0; c < b; ++c) {
+                const double2 cv = to_d(a.CV[r * a.ldc + c]);
+                double2 bvv = a.bv ? to_d(a.bv[r * a.ldb + c]) : cmul(sc, to_d(a.V[r * a.ldv + c]));
+                const double2 z = sZ[c + j * b];
+                cfma(bx, bvv, z);
+                cfma(ax, cadd(cv, cmul(a.sigma, bvv)), z);
+            }
+            const double2 rr = csub(ax, cmul(sl[j], bx));
+            acc.x += rr.x * rr.x + rr.y * rr.y;
+            acc.y += ax.x * ax.x + ax.y * ax.y;
+        }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < b) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int r = 0; r < rpt; ++r) s = cadd(s, red[r * b + tid]);
+        a.part[(int64_t)tid * a.nblk + blockIdx.x] = s;
+    }
+}
+
+template <typename T>
+int launch_resid_partials(hipStream_t st, int64_t n, int b, const T *CV, int ldc, const T *V,
+                          int ldv, const T *bv, int ldb, const T *bscale, double2 sigma,
+                          const double2 *Zr, const double2 *lam, double2 *part, int max_blocks) {
+    if (b < 1 || b > 32) throw Error(-1, "resid: width out of range");
+    ResidArgs<T> a{n, b, CV, ldc, V, ldv, bv, ldb, bscale, sigma, Zr, lam, part, 0, 0};
+    int nblk = (int)std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n + 255) / 256));
+    a.nblk = nblk;
+    a.rows_per_blk = (n + nblk - 1) / nblk;
+    hipLaunchKernelGGL((resid_kernel<T>), dim3(nblk), dim3(256), 0, st, a);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    return nblk;
+}
+template int launch_resid_partials<double2>(hipStream_t, int64_t, int, const double2 *, int,
+                                            const double2 *, int, const double2 *, int,
+                                            const double2 *, double2, const double2 *,
+                                            const double2 *, double2 *, int);
+template int launch_resid_partials<float2>(hipStream_t, int64_t, int, const float2 *, int,
+                                           const float2 *, int, const float2 *, int,
+                                           const float2 *, double2, const double2 *,
+                                           const double2 *, double2 *, int);
+
+// ---------------------------------------------------------------------------
+// seeded complex normal block
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+__global__ void randn_kernel(int64_t n, int w, uint64_t seed, double2 *out, int ldo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t i = e / w;
+    const int c = (int)(e - i * w);
+    const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * (uint64_t)e));
+    const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * (uint64_t)e + 1));
+    const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double rad = sqrt(-log(u1));   // variance 1/2 per component
+    const double th = 6.283185307179586 * u2;
+    out[i * ldo + c] = make_double2(rad * cos(th), rad * sin(th));
+}
+void launch_randn(hipStream_t st, int64_t n, int w, uint64_t seed, double2 *out, int ldo) {
+    hipLaunchKernelGGL(randn_kernel, dim3(ceil_div_i(n * w, 256)), dim3(256), 0, st, n, w, seed,
+                       out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// setup: validation, union pattern of C = A - sigma B, diagonal
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void csr_validate_kernel(int64_t n, const int32_t *rp,
+                                                           const int32_t *ci, const double2 *val,
+                                                           unsigned long long *counts) {
+    __shared__ unsigned long long sbad[2];
+    if (threadIdx.x < 2) sbad[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bad_row = 0, bad_val = 0;
+    if (i < n) {
+        const int p0 = rp[i], p1 = rp[i + 1];
+        if (p1 < p0) {
+            bad_row = 1;
+        } else {
+            int prev = -1;
+            for (int p = p0; p < p1; ++p) {
+                const int c = ci[p];
+                if (c <= prev || c >= n) bad_row = 1;
+                prev = c;
+                const double2 v = val[p];
+                if (!isfinite(v.x) || !isfinite(v.y)) bad_val += 1;
+            }
+        }
+    }
+    if (bad_row) atomicAdd(&sbad[0], bad_row);
+    if (bad_val) atomicAdd(&sbad[1], bad_val);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sbad[0]) atomicAdd(&counts[0], sbad[0]);
+        if (sbad[1]) atomicAdd(&counts[1], sbad[1]);
+    }
+}
+
+void csr_validate(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci,
+                  const double2 *val, int64_t *bad_rows, int64_t *bad_vals) {
+    unsigned long long *d = nullptr;
+    GPLHR_HIP_CHECK(hipMallocAsync((void **)&d, 2 * sizeof(unsigned long long), st));
+    GPLHR_HIP_CHECK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), st));
+    if (n > 0)
+        hipLaunchKernelGGL(csr_validate_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, rp,
+                           ci, val, d);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    unsigned long long h[2];
+    GPLHR_HIP_CHECK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFreeAsync(d, st));
+    *bad_rows = (int64_t)h[0];
+    *bad_vals = (int64_t)h[1];
+}
+
+__global__ void nondiag_kernel(int64_t n, const int32_t *rp, const int32_t *ci,
+                               unsigned long long *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], p1 = rp[i + 1];
+    if (p1 - p0 != 1 || ci[p0] != i) atomicAdd(cnt, 1ULL);
+}
+int64_t csr_count_nondiag_rows(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci) {
+    unsigned long long *d = nullptr;
+    GPLHR_HIP_CHECK(hipMallocAsync((void **)&d, sizeof(unsigned long long), st));
+    GPLHR_HIP_CHECK(hipMemsetAsync(d, 0, sizeof(unsigned long long), st));
+    if (n > 0)
+        hipLaunchKernelGGL(nondiag_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, rp, ci,
+                           d);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    unsigned long long h = 0;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFreeAsync(d, st));
+    return (int64_t)h;
+}
+
+// Merge walk of row i of A with row i of B (bkind 1) or with the single
+// diagonal column (bkind 0).  With out == nullptr only counts.
+__device__ int merge_row(int64_t i, const int32_t *arp, const int32_t *aci, const double2 *aval,
+                         int bkind, const int32_t *brp, const int32_t *bci, const double2 *bval,
+                         double2 sigma, int32_t *oci, double2 *oval) {
+    int pa = arp[i], ea = arp[i + 1];
+    int pb = 0, eb = 0;
+    if (bkind == 1) {
+        pb = brp[i];
+        eb = brp[i + 1];
+    }
+    bool diag_pending = (bkind == 0);
+    int cnt = 0;
+    while (true) {
+        int ca = pa < ea ? aci[pa] : INT32_MAX;
+        int cb;
+        if (bkind == 1)
+            cb = pb < eb ? bci[pb] : INT32_MAX;
+        else
+            cb = diag_pending ? (int)i : INT32_MAX;
+        if (ca == INT32_MAX && cb == INT32_MAX) break;
+        const int c = min(ca, cb);
+        double2 v = make_double2(0.0, 0.0);
+        if (ca == c) {
+            if (oval) v = aval[pa];
+            ++pa;
+        }
+        if (cb == c) {
+            double2 bv = make_double2(1.0, 0.0);
+            if (bkind == 1) {
+                if (oval) bv = bval[pb];
+                ++pb;
+            } else {
+                diag_pending = false;
+            }
+            if (oval) v = csub(v, cmul(sigma, bv));
+        }
+        if (oci) {
+            oci[cnt] = c;
+            oval[cnt] = v;
+        }
+        ++cnt;
+    }
+    return cnt;
+}
+
+__global__ void union_count_kernel(int64_t n, const int32_t *arp, const int32_t *aci, int bkind,
+                                   const int32_t *brp, const int32_t *bci, int32_t *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        cnt[n] = 0;
+        return;
+    }
+    cnt[i] = merge_row(i, arp, aci, nullptr, bkind, brp, bci, nullptr, make_double2(0, 0),
+                       nullptr, nullptr);
+}
+__global__ void union_fill_kernel(int64_t n, const int32_t *arp, const int32_t *aci,
+                                  const double2 *aval, int bkind, const int32_t *brp,
+                                  const int32_t *bci, const double2 *bval, double2 sigma,
+                                  const int32_t *crp, int32_t *cci, double2 *cval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int off = crp[i];
+    merge_row(i, arp, aci, aval, bkind, brp, bci, bval, sigma, cci + off, cval + off);
+}
+
+static void exclusive_scan_i32(hipStream_t st, const int32_t *in, int32_t *out, int64_t cnt) {
+    size_t tmp = 0;
+    GPLHR_HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, in, out, (int)cnt, st));
+    void *d_tmp = nullptr;
+    GPLHR_HIP_CHECK(hipMallocAsync(&d_tmp, tmp, st));
+    GPLHR_HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(d_tmp, tmp, in, out, (int)cnt, st));
+    GPLHR_HIP_CHECK(hipFreeAsync(d_tmp, st));
+}
+
+int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32_t *aci,
+                      const double2 *aval, int bkind, const int32_t *brp, const int32_t *bci,
+                      const double2 *bval, double2 sigma, int32_t **crp, int32_t **cci,
+                      double2 **cval) {
+    int32_t *cnt = nullptr, *rp = nullptr;
+    GPLHR_HIP_CHECK(hipMalloc((void **)&cnt, sizeof(int32_t) * (n + 1)));
+    GPLHR_HIP_CHECK(hipMalloc((void **)&rp, sizeof(int32_t) * (n + 1)));
+    hipLaunchKernelGGL(union_count_kernel, dim3(ceil_div_i(n + 1, 256)), dim3(256), 0, st, n, arp,
+                       aci, bkind, brp, bci, cnt);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    exclusive_scan_i32(st, cnt, rp, n + 1);
+    int32_t nnz = 0;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFree(cnt));
+    int32_t *ci = nullptr;
+    double2 *val = nullptr;
+    GPLHR_HIP_CHECK(hipMalloc((void **)&ci, sizeof(int32_t) * std::max<int64_t>(1, nnz)));
+    GPLHR_HIP_CHECK(hipMalloc((void **)&val, sizeof(double2) * std::max<int64_t>(1, nnz)));
+    hipLaunchKernelGGL(union_fill_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, arp, aci,
+                       aval, bkind, brp, bci, bval, sigma, rp, ci, val);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    *crp = rp;
+    *cci = ci;
+    *cval = val;
+    return nnz;
+}
+
+__global__ void diag_kernel(int64_t n, const int32_t *rp, const int32_t *ci, const double2 *val,
+                            double2 *d, unsigned long long *zeros) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    double2 v = make_double2(0.0, 0.0);
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = ci[mid];
+        if (c == i) {
+            v = val[mid];
+            break;
+        }
+        if (c < i)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    d[i] = v;
+    if (v.x == 0.0 && v.y == 0.0) atomicAdd(zeros, 1ULL);
+}
+int64_t extract_diag(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci,
+                     const double2 *val, double2 *d) {
+    unsigned long long *z = nullptr;
+    GPLHR_HIP_CHECK(hipMallocAsync((void **)&z, sizeof(unsigned long long), st));
+    GPLHR_HIP_CHECK(hipMemsetAsync(z, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(diag_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, rp, ci, val, d,
+                       z);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    unsigned long long h = 0;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(&h, z, sizeof(h), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFreeAsync(z, st));
+    return (int64_t)h;
+}
+
+__global__ void recip_kernel(int64_t n, const double2 *d, double2 num, double2 *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = d[i];
+    const double den = v.x * v.x + v.y * v.y;
+    // num / v = num * conj(v) / |v|^2
+    const double2 q = make_double2((num.x * v.x + num.y * v.y) / den, (num.y * v.x - num.x * v.y) / den);
+    out[i] = q;
+}
+void launch_recip_scaled(hipStream_t st, int64_t n, const double2 *d, double2 num, double2 *out) {
+    hipLaunchKernelGGL(recip_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, d, num, out);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// conjugate transpose of a CSR matrix (for the adjoint pencil)
+// ---------------------------------------------------------------------------
+__global__ void col_count_kernel(int64_t nnz, const int32_t *ci, int32_t *cnt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[ci[p]], 1);
+}
+// Scatter row by row: one thread per row of the source walks its entries in
+// order; positions inside a target row are taken with atomics and then sorted.
+__global__ void transpose_scatter_kernel(int64_t n, const int32_t *rp, const int32_t *ci,
+                                         const double2 *val, const int32_t *trp, int32_t *fill,
+                                         int32_t *tci, double2 *tval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int c = ci[p];
+        const int pos = trp[c] + atomicAdd(&fill[c], 1);
+        tci[pos] = (int32_t)i;
+        const double2 v = val[p];
+        tval[pos] = make_double2(v.x, -v.y);
+    }
+}
+__global__ void sort_rows_kernel(int64_t n, const int32_t *rp, int32_t *ci, double2 *val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], p1 = rp[i + 1];
+    for (int p = p0 + 1; p < p1; ++p) {   // insertion sort (rows are short)
+        const int c = ci[p];
+        const double2 v = val[p];
+        int q = p - 1;
+        while (q >= p0 && ci[q] > c) {
+            ci[q + 1] = ci[q];
+            val[q + 1] = val[q];
+            --q;
+        }
+        ci[q + 1] = c;
+        val[q + 1] = v;
+    }
+}
+void csr_conj_transpose(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp,
+                        const int32_t *ci, const double2 *val, int32_t **trp_o, int32_t **tci_o,
+                        double2 **tval_o) {
+    int32_t *cnt = nullptr, *trp = nullptr, *tci = nullptr;
+    double2 *tval = nullptr;
+    GPLHR_HIP_CHECK(hipMalloc((void **)&cnt, sizeof(int32_t) * (n + 1)));
+    GPLHR_HIP_CHECK(hipMalloc((void **)&trp, sizeof(int32_t) * (n + 1)));
+    GPLHR_HIP_CHECK(hipMalloc((void **)&tci, sizeof(int32_t) * std::max<int64_t>(1, nnz)));
+    GPLHR_HIP_CHECK(hipMalloc((void **)&tval, sizeof(double2) * std::max<int64_t>(1, nnz)));
+    GPLHR_HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
+    if (nnz > 0)
+        hipLaunchKernelGGL(col_count_kernel, dim3(ceil_div_i(nnz, 256)), dim3(256), 0, st, nnz, ci,
+                           cnt);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    exclusive_scan_i32(st, cnt, trp, n + 1);
+    GPLHR_HIP_CHECK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
+    hipLaunchKernelGGL(transpose_scatter_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, rp,
+                       ci, val, trp, cnt, tci, tval);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(sort_rows_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, trp, tci,
+                       tval);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFree(cnt));
+    *trp_o = trp;
+    *tci_o = tci;
+    *tval_o = tval;
+}
+
+// ---------------------------------------------------------------------------
+// sampled dense-dense product onto a CSR pattern
+// ---------------------------------------------------------------------------
+__global__ void sddmm_kernel(int64_t n, const int32_t *rp, const int32_t *ci, int k,
+                             const double2 *Y, int ldy, const double2 *X, int ldx,
+                             const double2 *coef, double2 *grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 yc[16];
+    for (int e = 0; e < k; ++e) yc[e] = cmul(coef[e], Y[i * ldy + e]);
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = 0; e < k; ++e) {
+            const double2 x = X[(int64_t)j * ldx + e];
+            // acc += yc * conj(x)
+            acc.x += yc[e].x * x.x + yc[e].y * x.y;
+            acc.y += yc[e].y * x.x - yc[e].x * x.y;
+        }
+        grad[p] = acc;
+    }
+}
+void launch_sddmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, int k,
+                  const double2 *Y, int ldy, const double2 *X, int ldx, const double2 *coef,
+                  double2 *grad) {
+    if (k < 1 || k > 16) throw Error(-1, "sddmm: k out of range");
+    hipLaunchKernelGGL(sddmm_kernel, dim3(ceil_div_i(n, 128)), dim3(128), 0, st, n, rp, ci, k, Y,
+                       ldy, X, ldx, coef, grad);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace gplhr

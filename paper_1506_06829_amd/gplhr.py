@@ -1,0 +1,285 @@
+"""Python binding of the GPLHR HIP library (argument marshalling only).
+
+Every computation runs inside ``libgplhr.so`` (hand-written HIP for gfx950 plus
+host C++ for the small projected step); this module only passes device
+pointers of torch tensors and the current HIP stream across the C ABI declared
+in ``include/gplhr.h``.  If the library has not been built, importing works but
+every call raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from pathlib import Path
+from typing import Optional
+
+import numpy as np
+import torch
+
+_LIB_PATH = Path(__file__).resolve().parent / "libgplhr.so"
+_lib = None
+
+OK, NOT_CONVERGED = 0, 1
+_STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_ALLOC", -3: "ERR_HIP",
+           -4: "ERR_BREAKDOWN", -5: "ERR_SINGULAR_SHIFT", -6: "ERR_NUMERIC",
+           -7: "ERR_NOT_SIMPLE", -8: "ERR_STATE"}
+PRECOND = {"none": 0, "diag": 1, "jacobi": 2}
+
+
+class GplhrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Precond(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("sweeps", ctypes.c_int), ("omega", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("arnoldi_m", ctypes.c_int), ("p_mode", ctypes.c_int), ("V0", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
+                ("switch_tol", ctypes.c_double), ("stall_window", ctypes.c_int),
+                ("timing", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("fp64_iterations", ctypes.c_int64),
+                ("spmm_calls", ctypes.c_int64), ("precond_calls", ctypes.c_int64),
+                ("breakdowns", ctypes.c_int64), ("spmm_ms", ctypes.c_double),
+                ("spmm_bytes", ctypes.c_double), ("gram_ms", ctypes.c_double),
+                ("update_ms", ctypes.c_double), ("small_host_ms", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
+                ("max_rel_resid", ctypes.c_double), ("n_converged", ctypes.c_int),
+                ("phase", ctypes.c_int)]
+
+
+EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
+           "gplhr_get_eigvecs", "gplhr_eig_backward", "gplhr_get_stats", "gplhr_destroy",
+           "gplhr_last_error", "gplhr_spmm", "gplhr_gram"]
+
+
+def lib():
+    """Load ``libgplhr.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_1506_06829_amd.build`")
+    L = ctypes.CDLL(str(_LIB_PATH))
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    L.gplhr_default_options.argtypes = [ctypes.POINTER(_Options)]
+    L.gplhr_default_options.restype = None
+    L.gplhr_create.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), dbl, dbl, i32, i32,
+                               ctypes.POINTER(_Precond), ctypes.POINTER(_Options), ctypes.POINTER(vp)]
+    L.gplhr_create.restype = i32
+    L.gplhr_iterate.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.gplhr_iterate.restype = i32
+    L.gplhr_get_schur.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.gplhr_get_schur.restype = i32
+    L.gplhr_get_eigvecs.argtypes = [vp, vp]
+    L.gplhr_get_eigvecs.restype = i32
+    L.gplhr_eig_backward.argtypes = [vp, vp, vp, vp]
+    L.gplhr_eig_backward.restype = i32
+    L.gplhr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+    L.gplhr_get_stats.restype = i32
+    L.gplhr_destroy.argtypes = [vp]
+    L.gplhr_destroy.restype = None
+    L.gplhr_last_error.argtypes = [vp]
+    L.gplhr_last_error.restype = ctypes.c_char_p
+    L.gplhr_spmm.argtypes = [i32, i64, vp, vp, vp, vp, i32, vp, i32, i32, vp]
+    L.gplhr_spmm.restype = i32
+    L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
+    L.gplhr_gram.restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int, handle=None) -> int:
+    if status < 0:
+        msg = lib().gplhr_last_error(handle)
+        raise GplhrError(status, msg.decode() if msg else "")
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceCsr:
+    """CSR matrix whose arrays live on the GPU (int32 indices, complex128 values)."""
+    n: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @staticmethod
+    def from_host(csr, device="cuda") -> "DeviceCsr":
+        """From any object with n / indptr / indices / data (e.g. problems.Csr)."""
+        return DeviceCsr(int(csr.n),
+                         torch.as_tensor(np.asarray(csr.indptr, dtype=np.int32)).to(device),
+                         torch.as_tensor(np.asarray(csr.indices, dtype=np.int32)).to(device),
+                         torch.as_tensor(np.asarray(csr.data, dtype=np.complex128)).to(device))
+
+    def _c(self) -> _Csr:
+        assert self.row_ptr.dtype == torch.int32 and self.col_idx.dtype == torch.int32
+        assert self.val.dtype == torch.complex128 and self.val.is_contiguous()
+        return _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                    self.val.data_ptr())
+
+
+class Solver:
+    """One GPLHR solve (a handle of the C library)."""
+
+    def __init__(self, A: DeviceCsr, B: Optional[DeviceCsr], sigma: complex, k: int,
+                 block: Optional[int] = None, precond: str = "diag", sweeps: int = 3,
+                 omega: float = 0.7, precision: str = "fp64", tol: float = 1e-10,
+                 max_iter: int = 500, m: int = 1, p_mode: str = "thick",
+                 V0: Optional[torch.Tensor] = None, seed: int = 1, timing: bool = False,
+                 switch_tol: float = 1e-5, stall_window: int = 20, stream=None):
+        L = lib()
+        self.n, self.k = A.n, k
+        self.block = block or k
+        self._keep = (A, B, V0)
+        opt = _Options()
+        L.gplhr_default_options(ctypes.byref(opt))
+        opt.precision = {"fp64": 0, "mixed": 1}[precision]
+        opt.tol = tol
+        opt.max_iter = max_iter
+        opt.arnoldi_m = m
+        opt.p_mode = {"thick": 0, "none": 2}[p_mode]
+        if V0 is not None:
+            assert V0.dtype == torch.complex128 and V0.is_contiguous()
+            assert tuple(V0.shape) == (A.n, self.block)
+            opt.V0 = V0.data_ptr()
+        opt.seed = seed
+        self._stream = torch.cuda.current_stream() if stream is None else stream
+        opt.hip_stream = self._stream.cuda_stream
+        opt.switch_tol = switch_tol
+        opt.stall_window = stall_window
+        opt.timing = 1 if timing else 0
+        pre = _Precond(PRECOND[precond], sweeps, omega)
+        a = A._c()
+        b = B._c() if B is not None else None
+        h = ctypes.c_void_p()
+        st = L.gplhr_create(ctypes.byref(a), ctypes.byref(b) if b is not None else None,
+                            float(complex(sigma).real), float(complex(sigma).imag), k,
+                            self.block, ctypes.byref(pre), ctypes.byref(opt), ctypes.byref(h))
+        _check(st, None)
+        self.h = h
+
+    def iterate(self, max_iter: int = 0):
+        nc = ctypes.c_int()
+        mr = ctypes.c_double()
+        st = _check(lib().gplhr_iterate(self.h, max_iter, ctypes.byref(nc), ctypes.byref(mr)), self.h)
+        return st, nc.value, mr.value
+
+    def schur(self, want_vectors: bool = True):
+        n, k = self.n, self.k
+        V = torch.empty((n, k), dtype=torch.complex128, device="cuda") if want_vectors else None
+        Q = torch.empty((n, k), dtype=torch.complex128, device="cuda") if want_vectors else None
+        RA = np.zeros((k, k), dtype=np.complex128, order="F")
+        RB = np.zeros((k, k), dtype=np.complex128, order="F")
+        lam = np.zeros(k, dtype=np.complex128)
+        rho = np.zeros(k, dtype=np.float64)
+        _check(lib().gplhr_get_schur(self.h, _ptr(V), _ptr(Q), RA.ctypes.data, RB.ctypes.data,
+                                     lam.ctypes.data, rho.ctypes.data), self.h)
+        return dict(V=V, Q=Q, RA=RA, RB=RB, lam=lam, rho=rho)
+
+    def eigvecs(self) -> torch.Tensor:
+        X = torch.empty((self.n, self.k), dtype=torch.complex128, device="cuda")
+        _check(lib().gplhr_get_eigvecs(self.h, _ptr(X)), self.h)
+        return X
+
+    def backward(self, grad_lambda: np.ndarray, nnzA: int, nnzB: Optional[int]):
+        g = np.ascontiguousarray(np.asarray(grad_lambda, dtype=np.complex128))
+        gA = torch.empty(nnzA, dtype=torch.complex128, device="cuda")
+        gB = torch.empty(nnzB, dtype=torch.complex128, device="cuda") if nnzB else None
+        _check(lib().gplhr_eig_backward(self.h, g.ctypes.data, _ptr(gA), _ptr(gB)), self.h)
+        return gA, gB
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().gplhr_get_stats(self.h, ctypes.byref(s)), self.h)
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().gplhr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
+         val: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Y = A X with the library's CSR kernel; complex128 or complex64 blocks
+    (``val`` overrides A's values, e.g. a complex64 copy)."""
+    v = A.val if val is None else val
+    dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+    assert v.dtype == X.dtype and X.dim() == 2 and X.stride(1) == 1
+    b = X.shape[1]
+    if Y is None:
+        Y = torch.empty((A.n, b), dtype=X.dtype, device=X.device)
+    _check(lib().gplhr_spmm(dtype, A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
+                            X.stride(0), _ptr(Y), Y.stride(0), b, _stream_ptr()))
+    return Y
+
+
+def gram(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+    """G = X^H Y (complex128, FP64 accumulation) with the library's kernel."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+    assert X.dtype == Y.dtype and X.stride(1) == 1 and Y.stride(1) == 1
+    bx, by = X.shape[1], Y.shape[1]
+    G = torch.empty((by, bx), dtype=torch.complex128, device=X.device)   # column-major bx x by
+    _check(lib().gplhr_gram(dtype, X.shape[0], _ptr(X), X.stride(0), bx, _ptr(Y), Y.stride(0),
+                            by, _ptr(G), _stream_ptr()))
+    return G.t()
+
+
+class GPLHREig(torch.autograd.Function):
+    """k eigenvalues of (A, B) nearest sigma as a differentiable function of
+    the stored values of A and B (hand-written backward through the adjoint
+    pencil and a sampled dense-dense product; see gplhr_eig_backward)."""
+
+    @staticmethod
+    def forward(ctx, valA, valB, A: DeviceCsr, B: Optional[DeviceCsr], sigma, k, opts):
+        A2 = DeviceCsr(A.n, A.row_ptr, A.col_idx, valA.detach().contiguous())
+        B2 = None if B is None else DeviceCsr(B.n, B.row_ptr, B.col_idx, valB.detach().contiguous())
+        s = Solver(A2, B2, sigma, k, **(opts or {}))
+        st, _, res = s.iterate()
+        if st != OK:
+            raise GplhrError(NOT_CONVERGED, f"forward solve did not converge (residual {res:.3e})")
+        lam = s.schur(want_vectors=False)["lam"]
+        ctx.solver = s
+        ctx.nnzA = A.nnz
+        ctx.nnzB = None if B is None else B.nnz
+        return torch.as_tensor(lam, dtype=torch.complex128, device=valA.device)
+
+    @staticmethod
+    def backward(ctx, grad_lam):
+        g = grad_lam.detach().to("cpu", torch.complex128).numpy()
+        gA, gB = ctx.solver.backward(g, ctx.nnzA, ctx.nnzB)
+        ctx.solver.close()
+        return gA, gB, None, None, None, None, None

@@ -132,6 +132,30 @@ def random_pencil(n: int, seed: int = 0, offdiag_per_row: int = 16,
     return csr_from_scipy(A), csr_from_scipy(B)
 
 
+def diag_dominant_pencil(n: int, seed: int = 0, offdiag_per_row: int = 16,
+                         coupling: float = 0.5, with_b: bool = True) -> tuple[Csr, Optional[Csr]]:
+    """Diagonally dominant sparse non-Hermitian pencil (the situation of
+    Section 1 where the diagonal makes an effective preconditioner).
+
+    A = D + E: D(i,i) uniform in [0, n) plus 0.1 i N(0,1); E has
+    ``offdiag_per_row`` uniformly drawn off-diagonal columns per row (drawn
+    with replacement, duplicates summed) with values coupling * CN(0,1).
+    B = diag U[1,2] from ``default_rng(0)`` (or None).
+    """
+    rng = np.random.default_rng(seed)
+    q = offdiag_per_row
+    d = rng.uniform(0.0, float(n), n) + 0.1j * rng.standard_normal(n)
+    rows = np.repeat(np.arange(n), q)
+    cols = rng.integers(0, n - 1, n * q)
+    cols[cols >= rows] += 1
+    vals = coupling * (rng.standard_normal(n * q) + 1j * rng.standard_normal(n * q)) / np.sqrt(2)
+    A = sp.coo_matrix((np.concatenate([vals, d]),
+                       (np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]))),
+                      shape=(n, n))
+    B = diag_csr(diagonal_b(n, 0)) if with_b else None
+    return csr_from_scipy(A), B
+
+
 def start_block(n: int, b: int, seed: int = 1) -> np.ndarray:
     rng = np.random.default_rng(seed)
     re = rng.standard_normal((n, b))
@@ -175,6 +199,9 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
     c4  random pencil n=131072, sigma=0, k=b=8, T=diag(C)^-1
     c5  3-D upwind, N=160 (n=4096000), c=(20,10,5), B=diag U[1,2],
         sigma=1000+100i, k=b=16, Jacobi-3, mixed precision
+    d1  diagonally dominant pencil (see diag_dominant_pencil), n=262144,
+        B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T=diag(C)^-1, complex128
+    d1m d1 in mixed precision
 
     ``scale`` overrides the grid size N (stencils) or n (random pencil) to give
     a smaller instance of the same family.
@@ -198,4 +225,9 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
         A = convection_diffusion(N, (20.0, 10.0, 5.0))
         B = diag_csr(diagonal_b(A.n, 0))
         return _with_v0(Problem("c5", A, B, 1000.0 + 100.0j, 16, 16, "jacobi", 3, 0.7, "mixed"))
+    if name in ("d1", "d1m"):
+        n = scale or 262144
+        A, B = diag_dominant_pencil(n, 0)
+        return _with_v0(Problem(name, A, B, n / 2 + 0.3j, 10, 10, "diag",
+                                precision="fp64" if name == "d1" else "mixed"))
     raise ValueError(f"unknown workload {name!r}")

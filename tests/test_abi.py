@@ -1,0 +1,61 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol that
+include/gplhr.h declares, and validates host-visible arguments (no GPU work)."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_symbols():
+    text = (ROOT / "include" / "gplhr.h").read_text()
+    return sorted(set(re.findall(r"\b(gplhr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ["gplhr_create", "gplhr_iterate", "gplhr_get_schur", "gplhr_eig_backward",
+              "gplhr_destroy", "gplhr_last_error", "gplhr_spmm", "gplhr_gram"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1506_06829_amd import gplhr
+    L = gplhr.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert set(gplhr.EXPORTS) <= set(declared_symbols())
+
+
+def test_default_options():
+    from paper_1506_06829_amd import gplhr
+    L = gplhr.lib()
+    o = gplhr._Options()
+    L.gplhr_default_options(ctypes.byref(o))
+    assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 500 and o.arnoldi_m == 1
+    assert o.p_mode == 0 and o.switch_tol == 1e-5 and o.stall_window == 20
+
+
+def test_argument_errors_without_device_work():
+    from paper_1506_06829_amd import gplhr
+    L = gplhr.lib()
+    h = ctypes.c_void_p()
+    # NULL A -> ERR_ARG, message available through gplhr_last_error(NULL)
+    st = L.gplhr_create(None, None, 0.0, 0.0, 1, 1, None, None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"A must be" in L.gplhr_last_error(None)
+    assert L.gplhr_create(None, None, 0.0, 0.0, 1, 1, None, None, None) == -1
+    # bad block widths for the single-kernel entry points
+    assert L.gplhr_spmm(0, 10, None, None, None, None, 4, None, 4, 0, None) == -1
+    assert L.gplhr_spmm(0, 10, None, None, None, None, 2, None, 4, 4, None) == -1
+    assert L.gplhr_gram(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
+    assert L.gplhr_iterate(None, 1, None, None) == -1
+
+
+def test_ctypes_structs_match_header():
+    from paper_1506_06829_amd import gplhr
+    # int64 n, nnz + three pointers
+    assert ctypes.sizeof(gplhr._Csr) == 40
+    assert ctypes.sizeof(gplhr._Precond) == 16

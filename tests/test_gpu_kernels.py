@@ -1,0 +1,82 @@
+"""Parity of the single HIP kernels (through the C ABI) with their definitions
+on the CPU: sparse matrix times block, and the FP64-accumulated Gram matrix."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1506_06829_amd import problems
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_csr(n, rng, max_row=40, empty_every=7):
+    rows, cols = [], []
+    for i in range(n):
+        if i % empty_every == 3:
+            continue                                  # empty rows
+        m = int(rng.integers(0, max_row))             # ragged lengths
+        c = np.unique(rng.integers(0, n, m))
+        rows += [i] * len(c)
+        cols += list(c)
+    v = rng.standard_normal(len(rows)) + 1j * rng.standard_normal(len(rows))
+    return problems.csr_from_scipy(sp.coo_matrix((v, (rows, cols)), shape=(n, n)))
+
+
+def _block(rng, n, b, ld=None):
+    ld = ld or b
+    X = rng.standard_normal((n, ld)) + 1j * rng.standard_normal((n, ld))
+    return X
+
+
+@pytest.mark.parametrize("b", [1, 3, 4, 10, 16, 33])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_spmm_matches_definition(device, b, dtype):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(b)
+    for csr in [_rand_csr(1001, rng), problems.convection_diffusion(9, (20.0, 10.0, 5.0))]:
+        n = csr.n
+        A = G.DeviceCsr.from_host(csr)
+        X = _block(rng, n, b, ld=b + 2)              # strided block: ld = b + 2
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        Xd = torch.as_tensor(X).to(device, tdt)[:, :b]
+        Y = G.spmm(A, Xd, val=A.val.to(tdt)).cpu().numpy()
+        ref = csr.to_scipy() @ X[:, :b].astype(np.complex64 if dtype == "c64" else np.complex128)
+        tol = 1e-14 if dtype == "c128" else 2e-6
+        scale = np.abs(csr.to_scipy()) @ np.abs(X[:, :b]) + 1e-300
+        assert np.max(np.abs(Y - ref) / scale) < tol
+        # bitwise reproducible
+        Y2 = G.spmm(A, Xd, val=A.val.to(tdt)).cpu().numpy()
+        assert np.array_equal(Y, Y2)
+
+
+def test_spmm_empty_matrix_rows(device):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    n = 50
+    csr = problems.Csr(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.complex128))
+    A = G.DeviceCsr.from_host(csr)
+    X = torch.ones((n, 4), dtype=torch.complex128, device=device)
+    Y = G.spmm(A, X).cpu().numpy()
+    assert np.all(Y == 0)
+
+
+@pytest.mark.parametrize("bx,by", [(1, 1), (5, 10), (10, 10), (16, 16), (30, 48), (48, 48), (64, 64)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 7, 1000, 100003])
+def test_gram_matches_definition(device, bx, by, dtype, n):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(bx * 100 + by)
+    X = _block(rng, n, bx)
+    Y = _block(rng, n, by)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    if dtype == "c64":
+        X = X.astype(np.complex64).astype(np.complex128)
+        Y = Y.astype(np.complex64).astype(np.complex128)
+    Xd, Yd = torch.as_tensor(X).to(device, tdt), torch.as_tensor(Y).to(device, tdt)
+    Gm = G.gram(Xd, Yd).cpu().numpy()
+    ref = X.conj().T @ Y
+    scale = np.abs(X).T @ np.abs(Y)
+    assert np.max(np.abs(Gm - ref) / scale) < 1e-13     # FP64 accumulation in both dtypes
+    assert np.array_equal(Gm, G.gram(Xd, Yd).cpu().numpy())
