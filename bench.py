@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-named", action="store_true", help="skip the named stencil workloads")
     ap.add_argument("--scale", type=int, default=None, help="override n of the default workload")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only the SpMM bandwidth measurement on the 160^3 operator (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -135,6 +137,18 @@ def main():
 
     from paper_1506_06829_amd import gplhr as G
     from paper_1506_06829_amd import problems
+
+    if args.spmm_only:
+        c5A = problems.convection_diffusion(160, (20.0, 10.0, 5.0))
+        res = {dt: spmm_hbm(G, torch, c5A, 16, dt) for dt in ("c64", "c128")}
+        # a plain device copy of known size, for scaling hardware byte counters
+        x = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"spmm_160cube_b16": res, "copy_bytes_each_way": x.numel() * 8}), flush=True)
+        return
 
     p = problems.config("d1m", args.scale)
     log(f"[bench] workload d1m n={p.n} nnz={p.A.nnz} k={p.k}")

@@ -206,7 +206,8 @@ gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad
             GPLHR_HIP_CHECK(hipMemcpy(c.coefY, P.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice));
             gplhr::UpdTerm<double2> t;
             t.in = Y; t.ld = k; t.col = 0; t.w = k; t.M = c.coefY; t.ldm = k;
-            gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+            gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t,
+                                          c.ucoef);
         }
         // y_e^H B x_e and ||B x_e||
         const double2 *bx = X;
@@ -304,12 +305,12 @@ gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr, const int3
             gplhr::launch_spmm<double2>(st, n, row_ptr, col_idx, static_cast<const double2 *>(val),
                                         static_cast<const double2 *>(X), ldx,
                                         static_cast<double2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
-                                        true);
+                                        false);
         else
             gplhr::launch_spmm<float2>(st, n, row_ptr, col_idx, static_cast<const float2 *>(val),
                                        static_cast<const float2 *>(X), ldx,
                                        static_cast<float2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
-                                       true);
+                                       false);
         return 0;
     });
 }
@@ -321,19 +322,17 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
             (dtype != 0 && dtype != 1) || !X || !Y || !G)
             throw gplhr::Error(-1, "gplhr_gram: bad arguments");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
-        const int maxb = 512;
+        const size_t cap = (size_t)1024 * bx * by;
         double2 *part = nullptr;
-        GPLHR_HIP_CHECK(hipMallocAsync((void **)&part, sizeof(double2) * maxb * bx * by, st));
-        int nblk;
+        GPLHR_HIP_CHECK(hipMallocAsync((void **)&part, sizeof(double2) * cap, st));
         if (dtype == 0)
-            nblk = gplhr::launch_gram_partials<double2>(st, n, static_cast<const double2 *>(X), ldx,
-                                                        bx, static_cast<const double2 *>(Y), ldy,
-                                                        by, nullptr, part, maxb);
+            gplhr::launch_gram<double2>(st, n, static_cast<const double2 *>(X), ldx, bx,
+                                        static_cast<const double2 *>(Y), ldy, by, nullptr, part,
+                                        cap, static_cast<double2 *>(G), bx);
         else
-            nblk = gplhr::launch_gram_partials<float2>(st, n, static_cast<const float2 *>(X), ldx,
-                                                       bx, static_cast<const float2 *>(Y), ldy, by,
-                                                       nullptr, part, maxb);
-        gplhr::launch_reduce_partials(st, part, nblk, bx, by, static_cast<double2 *>(G), bx);
+            gplhr::launch_gram<float2>(st, n, static_cast<const float2 *>(X), ldx, bx,
+                                       static_cast<const float2 *>(Y), ldy, by, nullptr, part, cap,
+                                       static_cast<double2 *>(G), bx);
         GPLHR_HIP_CHECK(hipFreeAsync(part, st));
         return 0;
     });

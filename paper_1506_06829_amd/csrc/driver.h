@@ -37,7 +37,8 @@ struct Timer {
 enum { T_SPMM = 0, T_GRAM = 1, T_UPDATE = 2 };
 
 struct Ctx {
-    static constexpr int PART_BLOCKS = 512;
+    static constexpr size_t PART_CAP = (size_t)1024 * 64 * 64;   // complex128 scratch entries
+    static constexpr int RESID_BLOCKS = 1024;
     static constexpr int EYE_N = 64;
     static constexpr int REFRESH_EVERY = 20;
 
@@ -49,7 +50,7 @@ struct Ctx {
     int k = 0, b = 0, m = 1, smax = 0;
     cd sigma;
     BKind bk = B_IDENT;
-    bool mixed = false, xcd_remap = true;
+    bool mixed = false, xcd_remap = false;
     int phase = 1;
     bool haveP = false, converged = false, checked = false;
 
@@ -76,6 +77,7 @@ struct Ctx {
     double2 *coefY = nullptr, *coefL = nullptr, *M1 = nullptr, *M2 = nullptr;
     double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
     double2 *xvec = nullptr;
+    double2 *ucoef = nullptr;   // combined update coefficients
     int *dstatus = nullptr;
     double2 *hpin = nullptr;   // pinned host staging
 

@@ -56,7 +56,7 @@ Ctx::~Ctx() {
     for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); }
     dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(eye); dfree(coefY); dfree(coefL);
     dfree(M1); dfree(M2); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
-    dfree(dstatus); dfree(xvec);
+    dfree(dstatus); dfree(xvec); dfree(ucoef);
     if (hpin) (void)hipHostFree(hpin);
 }
 
@@ -105,8 +105,7 @@ template <typename T>
 void Ctx::gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
                double2 *out) {
     tbegin(T_GRAM);
-    const int nblk = launch_gram_partials<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_BLOCKS);
-    launch_reduce_partials(st, part, nblk, bx, by, out, bx);
+    launch_gram<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_CAP, out, bx);
     tend(T_GRAM);
 }
 
@@ -115,7 +114,7 @@ void Ctx::update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool
                  int nterms, const UpdTerm<T> *terms) {
     tbegin(T_UPDATE);
     launch_update<T>(st, n, out, ldo, wout, ocol, split, ocol2,
-                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms);
+                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms, ucoef);
     tend(T_UPDATE);
 }
 
@@ -403,7 +402,7 @@ void Ctx::check() {
     GPLHR_HIP_CHECK(hipMemcpyAsync(dlam, hpin + bb, b * sizeof(double2), hipMemcpyHostToDevice, st));
     const int nblk = launch_resid_partials<T>(st, n, b, w.CZ, ld, w.Z, ld,
                                               bk == B_SPARSE ? w.BZ : nullptr, ld, bsc,
-                                              to_d2(sigma), dZr, dlam, part, PART_BLOCKS);
+                                              to_d2(sigma), dZr, dlam, part, RESID_BLOCKS);
     launch_reduce_partials(st, part, nblk, b, 1, rnorm, b);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb + b, rnorm, b * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
@@ -540,11 +539,12 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         dalloc(&wf.R, blk_b);
         if (pre.kind == GPLHR_PRECOND_JACOBI && pre.sweeps > 1) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
     }
-    dalloc(&part, (size_t)PART_BLOCKS * 64 * 64);
+    dalloc(&part, PART_CAP);
     dalloc(&g0, 64 * 64); dalloc(&g1, 64 * 64); dalloc(&rinv, 64 * 64);
     dalloc(&eye, EYE_N * EYE_N); dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
     dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
     dalloc(&dZr, 64 * 64); dalloc(&dlam, 64); dalloc(&rnorm, 64); dalloc(&dstatus, 1);
+    dalloc(&ucoef, 128 * 64);
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
     {
         std::vector<double2> e(EYE_N * EYE_N, make_double2(0.0, 0.0));
@@ -652,12 +652,12 @@ void Ctx::eigvecs(double2 *X) {
         dalloc(&tmp, (size_t)n * b);
         launch_c64_to_c128(st, n, b, wf.Z, smax, tmp, b);
         t.in = tmp; t.ld = b;
-        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t, ucoef);
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
         dfree(tmp);
     } else {
         t.in = wd.Z; t.ld = smax;
-        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t, ucoef);
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     }
 }

@@ -34,14 +34,13 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
                  const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
                  const T *dw, bool xcd_remap);
 
-// partial Gram sums of X^H (diag(yscale) Y); yscale (complex per row) may be
-// null.  Writes nblk partial bx-by-by matrices into `part` (entry-major:
-// part[e * nblk + blk], e = p + q*bx) and returns nblk.
+// G = X^H diag(yscale) Y (bx-by-by, FP64 accumulation, fixed reduction order)
+// written column-major with leading dimension ldo.  yscale (complex per row)
+// may be null.  `part` is scratch of part_cap complex128 entries.
 template <typename T>
-int launch_gram_partials(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
-                         int ldy, int by, const T *yscale, double2 *part, int max_blocks);
+void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo);
 
-// out[e * ldo_stride...]: out is column-major with leading dimension ldo:
 // out[p + q*ldo] = sum_blk part[(p + q*bx) * nblk + blk]  (fixed order)
 void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,
                             double2 *out, int ldo);
@@ -60,12 +59,14 @@ struct UpdTerm {
     const T *rowscale = nullptr;
 };
 
-// Out(:, map(c)) = beta * Out(:, map(c)) + sum_t term_t(:, c), c < wout, with
-// map(c) = ocol + c for c < split and ocol2 + (c - split) otherwise.  Row-local,
-// so Out may alias any input (every row is staged before it is written).
+// Out(:, map(c)) = beta * Out(:, map(c)) + sum_t term_t(:, c), c < wout <= 48,
+// with map(c) = ocol + c for c < split and ocol2 + (c - split) otherwise.
+// Row-local, so Out may alias any input.  `coef` is device scratch for the
+// combined coefficients (at least 128 * 48 complex128 entries), reused by
+// every call on the stream.
 template <typename T>
 void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
-                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms);
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef);
 
 // Cholesky-QR factor: given the w-by-w Gram G (column-major, Hermitian),
 // writes Rinv (column-major, upper triangular) with X Rinv orthonormal for

@@ -71,28 +71,31 @@ static inline int ceil_div_i(int64_t a, int64_t b) { return (int)((a + b - 1) / 
 // lane moves 16 bytes).  The row's index/value stream is read by all lanes of
 // the group at the same address (one broadcast transaction), the gathered
 // block rows are contiguous segments, and no cross-lane reduction is needed.
-template <typename T, int CPL>
-struct VecOf;
-template <> struct VecOf<double2, 1> { using V = double2; };
-template <> struct VecOf<float2, 1> { using V = float2; };
-template <> struct VecOf<float2, 2> { using V = float4; };
 
+// CPL consecutive complex values per lane, moved as 16-byte vectors.
 template <typename T, int CPL>
 __device__ __forceinline__ void load_vec(const T *p, T (&x)[CPL]) {
-    if constexpr (CPL == 1) {
-        x[0] = *p;
+    if constexpr (sizeof(T) == 16 || CPL == 1) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) x[c] = p[c];
     } else {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
-        x[0] = make_float2(v.x, v.y);
-        x[1] = make_float2(v.z, v.w);
+#pragma unroll
+        for (int c = 0; c < CPL; c += 2) {
+            const float4 v = *reinterpret_cast<const float4 *>(p + c);
+            x[c] = make_float2(v.x, v.y);
+            x[c + 1] = make_float2(v.z, v.w);
+        }
     }
 }
 template <typename T, int CPL>
 __device__ __forceinline__ void store_vec(T *p, const T (&x)[CPL]) {
-    if constexpr (CPL == 1) {
-        *p = x[0];
+    if constexpr (sizeof(T) == 16 || CPL == 1) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) p[c] = x[c];
     } else {
-        *reinterpret_cast<float4 *>(p) = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+#pragma unroll
+        for (int c = 0; c < CPL; c += 2)
+            *reinterpret_cast<float4 *>(p + c) = make_float4(x[c].x, x[c].y, x[c + 1].x, x[c + 1].y);
     }
 }
 
@@ -117,6 +120,8 @@ struct SpmmArgs {
     int per_xcd;    // >0: XCD-contiguous block remap
 };
 
+constexpr int SPMM_BATCH = 8;
+
 template <typename T, int CPL>
 __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     int blk = blockIdx.x;
@@ -132,45 +137,49 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     const int c0 = cl * CPL;
     if (rw >= a.rpw || row >= a.n || c0 >= a.b) return;
 
+    // epilogue operands first, so their latency overlaps the gather
+    T xo[CPL], rh[CPL], w = czero<T>();
+    if (a.mode == 1) {
+        load_vec<T, CPL>(a.X + row * a.ldx + c0, xo);
+        load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
+        w = a.dw[row];
+    }
     T acc[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) acc[u] = czero<T>();
     const int p0 = a.rp[row], p1 = a.rp[row + 1];
     const T *__restrict__ Xc = a.X + c0;
-    int p = p0;
-    for (; p + 4 <= p1; p += 4) {
-        int j[4];
-        T v[4];
+    // whole batches of the row's index/value stream are in flight before the
+    // dependent block-row gathers are issued
+    for (int p = p0; p < p1; p += SPMM_BATCH) {
+        int j[SPMM_BATCH];
+        T v[SPMM_BATCH];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            j[u] = a.ci[p + u];
-            v[u] = a.val[p + u];
+        for (int u = 0; u < SPMM_BATCH; ++u) {
+            const bool ok = p + u < p1;
+            j[u] = ok ? a.ci[p + u] : -1;
+            v[u] = ok ? a.val[p + u] : czero<T>();
         }
-        T x[4][CPL];
+        T x[SPMM_BATCH][CPL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) load_vec<T, CPL>(Xc + (int64_t)j[u] * a.ldx, x[u]);
+        for (int u = 0; u < SPMM_BATCH; ++u) {
+            if (j[u] >= 0) {
+                load_vec<T, CPL>(Xc + (int64_t)j[u] * a.ldx, x[u]);
+            } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+                for (int c = 0; c < CPL; ++c) x[u][c] = czero<T>();
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SPMM_BATCH; ++u)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cfma(acc[c], v[u], x[u][c]);
-    }
-    for (; p < p1; ++p) {
-        const int j = a.ci[p];
-        const T v = a.val[p];
-        T x[CPL];
-        load_vec<T, CPL>(Xc + (int64_t)j * a.ldx, x);
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) cfma(acc[c], v, x[c]);
     }
     T out[CPL];
     if (a.mode == 0) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) out[c] = acc[c];
     } else {
-        T xo[CPL], rh[CPL];
-        load_vec<T, CPL>(a.X + row * a.ldx + c0, xo);
-        load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
-        const T w = a.dw[row];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             out[c] = xo[c];
@@ -186,13 +195,19 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
                  const T *dw, bool xcd_remap) {
     if (n <= 0) return;
     SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0};
-    bool two = false;
+    // lanes move 32 bytes of the block row: 4 complex64 or 2 complex128 values
+    const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
+                            (mode == 1 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
+    int cpl = 1;
     if constexpr (sizeof(T) == 8) {
-        two = (b % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) && (mode == 0 || ldr % 2 == 0) &&
-              ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % 16 == 0) &&
-              (mode == 0 || reinterpret_cast<uintptr_t>(Rhs) % 16 == 0);
+        const bool ok4 = (b % 4 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) &&
+                         (mode == 0 || ldr % 2 == 0) && align % 16 == 0;
+        const bool ok2 = (b % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) &&
+                         (mode == 0 || ldr % 2 == 0) && align % 16 == 0;
+        cpl = ok4 ? 4 : (ok2 ? 2 : 1);
+    } else {
+        cpl = (b % 2 == 0) ? 2 : 1;
     }
-    const int cpl = two ? 2 : 1;
     a.lpr = (b + cpl - 1) / cpl;
     if (a.lpr > 64) throw Error(-1, "spmm: block too wide");
     a.rpw = 64 / a.lpr;
@@ -204,14 +219,12 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
         grid = (nblocks + 7) / 8 * 8;
         a.per_xcd = grid / 8;
     }
-    if constexpr (sizeof(T) == 8) {
-        if (two)
-            hipLaunchKernelGGL((spmm_kernel<T, 2>), dim3(grid), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a);
-    } else {
+    if (cpl == 4)
+        hipLaunchKernelGGL((spmm_kernel<T, 4>), dim3(grid), dim3(256), 0, st, a);
+    else if (cpl == 2)
+        hipLaunchKernelGGL((spmm_kernel<T, 2>), dim3(grid), dim3(256), 0, st, a);
+    else
         hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a);
-    }
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
@@ -223,12 +236,15 @@ template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const i
                                   const float2 *, int, const float2 *, bool);
 
 // ---------------------------------------------------------------------------
-// Gram partials G_blk = X(rows_blk,:)^H diag(yscale) Y(rows_blk,:), FP64
+// Gram matrices G = X^H diag(yscale) Y in FP64, deterministic
 // ---------------------------------------------------------------------------
-// Threads form groups; each group covers the whole bx-by-by output with
-// RX-by-RY register tiles and walks a strided subset of the block's rows.
-// Groups are summed in LDS in a fixed order, so results are bitwise
-// reproducible run to run.
+// Narrow X (bx <= 16): a lane owns one column q of Y and all bx columns of
+// X; the `lq` lanes of a group cover one row, so a wavefront reads 64/lq whole
+// rows of Y per instruction while the X entries of a row are broadcast (16-byte
+// loads).  Row slots are combined with wavefront shuffles and the four waves'
+// row groups in LDS, both in a fixed order.
+constexpr int GPB = 16;
+
 template <typename T>
 struct GramArgs {
     int64_t n;
@@ -241,109 +257,235 @@ struct GramArgs {
     const T *yscale;
     double2 *part;
     int nblk;
-    int64_t rows_per_blk;
-    int tx, ty;
+    int lq;     // lanes per row (power of two >= by)
 };
 
-template <typename T, int RX, int RY>
+template <typename T, bool PAIR>
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a) {
-    extern __shared__ double2 sh_gram[];
-    const int tid = threadIdx.x;
-    const int nt = a.tx * a.ty;
-    const int groups = 256 / nt;
-    const int g = tid / nt;
-    const int t = tid - g * nt;
-    const int ti = t % a.tx, tj = t / a.tx;
-    const int p0 = ti * RX, q0 = tj * RY;
-    double2 acc[RX][RY];
+    __shared__ double2 red[GPB * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lq = a.lq, rs = 64 / lq;
+    const int slot = lane / lq, q = lane - slot * lq;
+    const int pn = a.bx;
+    double2 acc[GPB];
 #pragma unroll
-    for (int i = 0; i < RX; ++i)
+    for (int i = 0; i < GPB; ++i) acc[i] = make_double2(0.0, 0.0);
+    if (q < a.by) {
+        const int64_t stride = (int64_t)a.nblk * 4 * rs;
+        for (int64_t r = ((int64_t)blockIdx.x * 4 + wave) * rs + slot; r < a.n; r += stride) {
+            double2 y = to_d(a.Y[r * a.ldy + q]);
+            if (a.yscale) y = cmul(to_d(a.yscale[r]), y);
+            double2 xv[GPB];
+            if constexpr (PAIR) {
+                const float4 *xr = reinterpret_cast<const float4 *>(a.X + r * a.ldx);
 #pragma unroll
-        for (int j = 0; j < RY; ++j) acc[i][j] = make_double2(0.0, 0.0);
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_blk;
-    const int64_t r1 = min(a.n, r0 + a.rows_per_blk);
-    if (g < groups) {
-        for (int64_t r = r0 + g; r < r1; r += groups) {
-            double2 xv[RX], yv[RY];
-            const T *xr = a.X + r * a.ldx;
-            const T *yr = a.Y + r * a.ldy;
+                for (int i = 0; i < GPB / 2; ++i) {
+                    const float4 t = (2 * i < pn) ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    xv[2 * i] = make_double2(t.x, t.y);
+                    xv[2 * i + 1] = make_double2(t.z, t.w);
+                }
+            } else {
+                const T *xr = a.X + r * a.ldx;
 #pragma unroll
-            for (int i = 0; i < RX; ++i)
-                xv[i] = (p0 + i < a.bx) ? to_d(xr[p0 + i]) : make_double2(0.0, 0.0);
-            double2 sc = make_double2(1.0, 0.0);
-            if (a.yscale) sc = to_d(a.yscale[r]);
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                double2 y = (q0 + j < a.by) ? to_d(yr[q0 + j]) : make_double2(0.0, 0.0);
-                yv[j] = a.yscale ? cmul(sc, y) : y;
+                for (int i = 0; i < GPB; ++i) xv[i] = (i < pn) ? to_d(xr[i]) : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                for (int j = 0; j < RY; ++j) cfma_cj(acc[i][j], xv[i], yv[j]);
+            for (int i = 0; i < GPB; ++i) cfma_cj(acc[i], xv[i], y);
         }
     }
-    const int nent = a.bx * a.by;
-    if (groups == 1) {
+    for (int off = lq; off < 64; off <<= 1) {
 #pragma unroll
-        for (int i = 0; i < RX; ++i)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                const int p = p0 + i, q = q0 + j;
-                if (g == 0 && p < a.bx && q < a.by)
-                    a.part[(int64_t)(p + q * a.bx) * a.nblk + blockIdx.x] = acc[i][j];
-            }
-        return;
+        for (int i = 0; i < GPB; ++i) {
+            acc[i].x += __shfl_xor(acc[i].x, off);
+            acc[i].y += __shfl_xor(acc[i].y, off);
+        }
     }
-    for (int gg = 0; gg < groups; ++gg) {
-        if (g == gg) {
+    const bool owner = slot == 0 && q < a.by;
+    for (int g = 0; g < 4; ++g) {
+        if (owner && wave == g) {
 #pragma unroll
-            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                for (int j = 0; j < RY; ++j) {
-                    const int p = p0 + i, q = q0 + j;
-                    if (p < a.bx && q < a.by) {
-                        const int e = p + q * a.bx;
-                        sh_gram[e] = (gg == 0) ? acc[i][j] : cadd(sh_gram[e], acc[i][j]);
-                    }
+            for (int i = 0; i < GPB; ++i) {
+                if (i < pn) {
+                    const int e = i + q * a.bx;
+                    red[e] = (g == 0) ? acc[i] : cadd(red[e], acc[i]);
                 }
+            }
         }
         __syncthreads();
     }
-    for (int e = tid; e < nent; e += 256) a.part[(int64_t)e * a.nblk + blockIdx.x] = sh_gram[e];
+    for (int e = threadIdx.x; e < a.bx * a.by; e += 256)
+        a.part[(int64_t)e * a.nblk + blockIdx.x] = red[e];
 }
 
+// Wide X (bx > 16): the complex product is the real GEMM
+// [Re X, Im X]^T [Re Y, Im Y] over the interleaved real views (n x 2bx and
+// n x 2by), computed with FP64 matrix instructions (16x16x4, FP64 accumulate;
+// complex64 inputs are widened, so every product is exact).  The waves of a
+// block split the N tiles (and the rows, when there are few N tiles); each
+// block owns a contiguous row range and writes a real partial Gram.
 template <typename T>
-int launch_gram_partials(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
-                         int ldy, int by, const T *yscale, double2 *part, int max_blocks) {
-    if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
-    GramArgs<T> a{};
-    a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
-    a.yscale = yscale; a.part = part;
-    const bool big = (bx * by > 400);
-    const int RX = big ? 4 : 2, RY = big ? 4 : 2;
-    a.tx = (bx + RX - 1) / RX;
-    a.ty = (by + RY - 1) / RY;
-    if (a.tx * a.ty > 256) throw Error(-1, "gram: tile too large");
-    const int64_t min_rows = 128;
-    int nblk = (int)std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n + min_rows - 1) / min_rows));
-    a.nblk = nblk;
-    a.rows_per_blk = (n + nblk - 1) / nblk;
-    const int groups = 256 / (a.tx * a.ty);
-    const size_t shmem = groups > 1 ? sizeof(double2) * bx * by : 0;
-    if (big)
-        hipLaunchKernelGGL((gram_kernel<T, 4, 4>), dim3(nblk), dim3(256), shmem, st, a);
-    else
-        hipLaunchKernelGGL((gram_kernel<T, 2, 2>), dim3(nblk), dim3(256), shmem, st, a);
-    GPLHR_HIP_CHECK(hipGetLastError());
-    return nblk;
+struct GramMArgs {
+    int64_t n;
+    const T *X;
+    int ldx;
+    int bx;
+    const T *Y;
+    int ldy;
+    int by;
+    const T *yscale;
+    double *part;
+    int nblk;
+    int64_t rows_per_blk;
+    int MT, NT, G, ks;
+};
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+
+template <typename T> struct RealOf;
+template <> struct RealOf<double2> { using R = double; };
+template <> struct RealOf<float2> { using R = float; };
+
+constexpr int GM_U = 4;   // K steps (of 4 rows) whose operands are loaded ahead
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
+    using R = typename RealOf<T>::R;
+    __shared__ double red[2][8][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = wave % a.G, h = wave / a.G;
+    const bool active = h < a.ks;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nbx = 2 * a.bx, nby = 2 * a.by;
+    d4v acc[8][2];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[mt][t] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int64_t rb = (int64_t)blockIdx.x * a.rows_per_blk;
+    const int64_t re = min(a.n, rb + a.rows_per_blk);
+    const int64_t kstep = 4LL * a.ks;
+    if (active) {
+        for (int64_t r0 = rb + 4 * h; r0 < re; r0 += kstep * GM_U) {
+            R av[GM_U][8];
+            double bv[GM_U][2];
+#pragma unroll
+            for (int u = 0; u < GM_U; ++u) {
+                const int64_t r = r0 + kstep * u + lk;
+                const bool ok = r < re;
+                const R *xrow = reinterpret_cast<const R *>(a.X + r * a.ldx);
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    const int i = mt * 16 + li;
+                    av[u][mt] = (mt < a.MT && ok && i < nbx) ? xrow[i] : (R)0;
+                }
+                const R *yrow = reinterpret_cast<const R *>(a.Y + r * a.ldy);
+                double2 sc = make_double2(1.0, 0.0);
+                if (a.yscale && ok) sc = to_d(a.yscale[r]);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int nt = g + t * a.G;
+                    const int j = nt * 16 + li;
+                    double v = 0.0;
+                    if (nt < a.NT && ok && j < nby) {
+                        if (a.yscale) {
+                            // (sc * y) for the complex entry that holds real j
+                            const double yr = yrow[j & ~1], yi = yrow[j | 1];
+                            v = (j & 1) ? (sc.x * yi + sc.y * yr) : (sc.x * yr - sc.y * yi);
+                        } else {
+                            v = yrow[j];
+                        }
+                    }
+                    bv[u][t] = v;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < GM_U; ++u)
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    if (mt < a.MT) {
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            if (g + t * a.G < a.NT)
+                                acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                    (double)av[u][mt], bv[u][t], acc[mt][t], 0, 0, 0);
+                    }
+                }
+        }
+    }
+    // D(i, j) of a 16x16 tile (FP64 16x16x4 layout on gfx950): register v of
+    // lane l holds i = 4 v + l / 16, j = l % 16
+    auto store = [&](int mt, int nt, const d4v &d) {
+        const int j = nt * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = mt * 16 + 4 * v + lk;
+            if (i < nbx && j < nby) a.part[(int64_t)(i + j * nbx) * a.nblk + blockIdx.x] = d[v];
+        }
+    };
+    if (a.ks == 1) {
+        if (active) {
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (mt < a.MT && g + t * a.G < a.NT) store(mt, g + t * a.G, acc[mt][t]);
+        }
+        return;
+    }
+    // ks > 1: one N tile per wave group; the row splits are summed in LDS in order h
+    for (int hh = 0; hh < a.ks; ++hh) {
+        if (h == hh) {
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                if (mt < a.MT) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double &dst = red[g][mt][lane * 4 + v];
+                        dst = (hh == 0) ? acc[mt][0][v] : dst + acc[mt][0][v];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (h == 0 && g < a.NT) {
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            if (mt < a.MT) {
+                d4v d;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) d[v] = red[g][mt][lane * 4 + v];
+                store(mt, g, d);
+            }
+        }
+    }
 }
-template int launch_gram_partials<double2>(hipStream_t, int64_t, const double2 *, int, int,
-                                           const double2 *, int, int, const double2 *, double2 *,
-                                           int);
-template int launch_gram_partials<float2>(hipStream_t, int64_t, const float2 *, int, int,
-                                          const float2 *, int, int, const float2 *, double2 *,
-                                          int);
+
+// complex G(p, q) from the real partials: (rr + ii) + i (ri - ir)
+__global__ __launch_bounds__(256) void reduce_real_partials_kernel(const double *part, int nblk,
+                                                                  int bx, double2 *out, int ldo) {
+    __shared__ double2 sh[256];
+    const int e = blockIdx.x;
+    const int p = e % bx, q = e / bx;
+    const int nbx = 2 * bx;
+    const double *rr = part + (int64_t)((2 * p) + (2 * q) * nbx) * nblk;
+    const double *ii = part + (int64_t)((2 * p + 1) + (2 * q + 1) * nbx) * nblk;
+    const double *ri = part + (int64_t)((2 * p) + (2 * q + 1) * nbx) * nblk;
+    const double *ir = part + (int64_t)((2 * p + 1) + (2 * q) * nbx) * nblk;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nblk; i += 256) {
+        acc.x += rr[i] + ii[i];
+        acc.y += ri[i] - ir[i];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[p + (int64_t)q * ldo] = sh[0];
+}
 
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double2 *part, int nblk,
                                                               int bx, double2 *out, int ldo) {
@@ -371,9 +513,71 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
+template <typename T>
+void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo) {
+    if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
+    if (n <= 0) throw Error(-1, "gram: empty block");
+    if (bx <= GPB && by <= GPB) {
+        GramArgs<T> a{};
+        a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
+        a.yscale = yscale; a.part = part;
+        int lq = 1;
+        while (lq < by) lq <<= 1;
+        a.lq = lq;
+        const int64_t rows_per_pass = 4LL * (64 / lq);
+        const int64_t want = (n + rows_per_pass * 16 - 1) / (rows_per_pass * 16);
+        int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, want));
+        nblk = (int)std::min<size_t>(nblk, part_cap / ((size_t)bx * by));
+        a.nblk = nblk;
+        bool pair = false;
+        if constexpr (sizeof(T) == 8)
+            pair = (bx % 2 == 0) && (ldx % 2 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+        if (pair)
+            hipLaunchKernelGGL((gram_kernel<T, true>), dim3(nblk), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((gram_kernel<T, false>), dim3(nblk), dim3(256), 0, st, a);
+        GPLHR_HIP_CHECK(hipGetLastError());
+        launch_reduce_partials(st, part, nblk, bx, by, out, ldo);
+        return;
+    }
+    GramMArgs<T> a{};
+    a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
+    a.yscale = yscale;
+    a.part = reinterpret_cast<double *>(part);
+    a.MT = (2 * bx + 15) / 16;
+    a.NT = (2 * by + 15) / 16;
+    a.G = std::min(4, a.NT);
+    a.ks = 4 / a.G;
+    const size_t per_blk = (size_t)4 * bx * by;   // doubles
+    int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 511) / 512));
+    nblk = (int)std::min<size_t>(nblk, (2 * part_cap) / per_blk);
+    if (nblk < 1) throw Error(-1, "gram: partial buffer too small");
+    a.nblk = nblk;
+    const int64_t step = 4LL * a.ks;
+    a.rows_per_blk = ((n + nblk - 1) / nblk + step - 1) / step * step;
+    hipLaunchKernelGGL((gram_mfma_kernel<T>), dim3(nblk), dim3(256), 0, st, a);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(bx * by), dim3(256), 0, st, a.part, nblk,
+                       bx, out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
+                                   const double2 *, int, int, const double2 *, double2 *, size_t,
+                                   double2 *, int);
+template void launch_gram<float2>(hipStream_t, int64_t, const float2 *, int, int, const float2 *,
+                                  int, int, const float2 *, double2 *, size_t, double2 *, int);
+
 // ---------------------------------------------------------------------------
-// row-local block update through LDS
+// row-local block update
 // ---------------------------------------------------------------------------
+// A small prep kernel folds alpha into the coefficient matrices and stores
+// them row-major in the block precision; the update kernel then gives every
+// lane one row: it streams the row's inputs with 16-byte loads and keeps the
+// wout accumulators in registers, while the coefficients (the same for every
+// lane) come through scalar loads.  A row is read and written by its own lane
+// only, with all of its loads issued before its stores, so Out may alias any
+// input.
 template <typename T>
 struct UpdArgs {
     int64_t n;
@@ -382,86 +586,75 @@ struct UpdArgs {
     double2 beta;
     int nterms;
     UpdTerm<T> t[3];
-    int wtot;   // sum of term widths
-    int tr;     // rows per block
+    int wtot;
+    const T *coef;   // wtot x wout, row-major, alpha folded
 };
 
 template <typename T>
+__global__ __launch_bounds__(256) void coef_prep_kernel(UpdArgs<T> a, T *coef) {
+    int base = 0;
+    for (int t = 0; t < a.nterms; ++t) {
+        const int w = a.t[t].w;
+        for (int e = threadIdx.x; e < w * a.wout; e += 256) {
+            const int j = e / a.wout, c = e - j * a.wout;
+            const double2 m = a.t[t].M[j + (int64_t)c * a.t[t].ldm];
+            coef[(base + j) * a.wout + c] = from_d<T>(cmul(a.t[t].alpha, m));
+        }
+        base += w;
+    }
+}
+
+template <typename T, int WO>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
-    extern __shared__ double2 sh_upd_raw[];
-    T *sM = reinterpret_cast<T *>(sh_upd_raw);                 // wtot x wout
-    T *sIn = sM + (size_t)a.wtot * a.wout;                      // tr x (wtot+1)
-    const int ldi = a.wtot + 1;
-    const int tid = threadIdx.x;
-    // coefficients, alpha folded in
-    {
-        int base = 0;
-        for (int t = 0; t < a.nterms; ++t) {
-            const int w = a.t[t].w;
-            for (int e = tid; e < w * a.wout; e += 256) {
-                const int j = e % w, c = e / w;
-                const double2 m = a.t[t].M[j + (int64_t)c * a.t[t].ldm];
-                sM[(base + j) * a.wout + c] = from_d<T>(cmul(a.t[t].alpha, m));
-            }
-            base += w;
-        }
-    }
-    const int64_t row0 = (int64_t)blockIdx.x * a.tr;
-    const int rows = (int)min((int64_t)a.tr, a.n - row0);
-    {
-        int base = 0;
-        for (int t = 0; t < a.nterms; ++t) {
-            const int w = a.t[t].w;
-            const T *in = a.t[t].in;
-            const T *rs = a.t[t].rowscale;
-            for (int e = tid; e < rows * w; e += 256) {
-                const int r = e / w, j = e - r * w;
-                const int64_t gi = row0 + r;
-                T v = in[gi * a.t[t].ld + a.t[t].col + j];
-                if (rs) v = cmul(rs[gi], v);
-                sIn[r * ldi + base + j] = v;
-            }
-            base += w;
-        }
-    }
-    // old values of the output (beta != 0), read before any write
-    constexpr int MAXP = 8;
-    T old[MAXP];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= a.n) return;
+    T acc[WO];
+#pragma unroll
+    for (int c = 0; c < WO; ++c) acc[c] = czero<T>();
     const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
-    const int npairs = rows * a.wout;
-    int k = 0;
-    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
-        if (use_beta) {
-            const int r = e / a.wout, c = e - r * a.wout;
-            const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
-            old[k] = a.out[(row0 + r) * a.ldo + oc];
+    const T *__restrict__ coef = a.coef;
+    int base = 0;
+    for (int t = 0; t < a.nterms; ++t) {
+        const T *in = a.t[t].in + r * a.t[t].ld + a.t[t].col;
+        const int w = a.t[t].w;
+        const T rs = a.t[t].rowscale ? a.t[t].rowscale[r] : from_d<T>(make_double2(1.0, 0.0));
+        const bool scale = a.t[t].rowscale != nullptr;
+        for (int j = 0; j < w; ++j) {
+            T x = in[j];
+            if (scale) x = cmul(rs, x);
+            const T *mrow = coef + (base + j) * a.wout;
+#pragma unroll
+            for (int c = 0; c < WO; ++c)
+                if (c < a.wout) cfma(acc[c], x, mrow[c]);
+        }
+        base += w;
+    }
+    T *orow = a.out + r * a.ldo;
+    if (use_beta) {
+        const T beta = from_d<T>(a.beta);
+#pragma unroll
+        for (int c = 0; c < WO; ++c) {
+            if (c < a.wout) {
+                const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+                cfma(acc[c], beta, orow[oc]);
+            }
         }
     }
-    __syncthreads();
-    T res[MAXP];
-    k = 0;
-    const T beta = from_d<T>(a.beta);
-    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
-        const int r = e / a.wout, c = e - r * a.wout;
-        T acc = czero<T>();
-        const T *xi = sIn + r * ldi;
-        for (int j = 0; j < a.wtot; ++j) cfma(acc, xi[j], sM[j * a.wout + c]);
-        if (use_beta) cfma(acc, beta, old[k]);
-        res[k] = acc;
-    }
-    k = 0;
-    for (int e = tid; e < npairs && k < MAXP; e += 256, ++k) {
-        const int r = e / a.wout, c = e - r * a.wout;
-        const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
-        a.out[(row0 + r) * a.ldo + oc] = res[k];
+#pragma unroll
+    for (int c = 0; c < WO; ++c) {
+        if (c < a.wout) {
+            const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+            orow[oc] = acc[c];
+        }
     }
 }
 
 template <typename T>
 void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
-                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms) {
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef) {
     if (n <= 0) return;
-    if (nterms < 0 || nterms > 3 || wout < 1 || wout > 64) throw Error(-1, "update: bad shape");
+    if (nterms < 1 || nterms > 3 || wout < 1 || wout > 48) throw Error(-1, "update: bad shape");
+    if (!coef) throw Error(-1, "update: no coefficient scratch");
     UpdArgs<T> a{};
     a.n = n; a.out = out; a.ldo = ldo; a.wout = wout; a.ocol = ocol; a.split = split;
     a.ocol2 = ocol2; a.beta = beta; a.nterms = nterms;
@@ -472,23 +665,24 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     }
     if (wtot < 1 || wtot > 128) throw Error(-1, "update: input too wide");
     a.wtot = wtot;
-    const size_t esz = sizeof(T);
-    const size_t budget = 64 * 1024;
-    const size_t msz = (size_t)wtot * wout * esz;
-    size_t tr = (budget - msz) / ((size_t)(wtot + 1) * esz);
-    tr = std::min<size_t>(tr, 2048 / (size_t)wout);   // at most 8 outputs per thread
-    tr = std::min<size_t>(tr, 64);
-    if (tr < 1) throw Error(-1, "update: LDS budget exceeded");
-    a.tr = (int)tr;
-    const size_t shmem = msz + tr * (wtot + 1) * esz;
-    const int grid = ceil_div_i(n, (int64_t)tr);
-    hipLaunchKernelGGL((update_kernel<T>), dim3(grid), dim3(256), shmem, st, a);
+    a.coef = static_cast<const T *>(coef);
+    hipLaunchKernelGGL((coef_prep_kernel<T>), dim3(1), dim3(256), 0, st, a, static_cast<T *>(coef));
+    GPLHR_HIP_CHECK(hipGetLastError());
+    const int grid = (int)((n + 255) / 256);
+    if (wout <= 8)
+        hipLaunchKernelGGL((update_kernel<T, 8>), dim3(grid), dim3(256), 0, st, a);
+    else if (wout <= 16)
+        hipLaunchKernelGGL((update_kernel<T, 16>), dim3(grid), dim3(256), 0, st, a);
+    else if (wout <= 32)
+        hipLaunchKernelGGL((update_kernel<T, 32>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((update_kernel<T, 48>), dim3(grid), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
-                                     double2, int, const UpdTerm<double2> *);
+                                     double2, int, const UpdTerm<double2> *, void *);
 template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, int, int, int,
-                                    double2, int, const UpdTerm<float2> *);
+                                    double2, int, const UpdTerm<float2> *, void *);
 
 // ---------------------------------------------------------------------------
 // Cholesky-QR factor (one workgroup, w <= 64)
