@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     const int64_t kstep = 4LL * a.ks;
     if (active) {
         for (int64_t r0 = rb + 4 * h; r0 < re; r0 += kstep * GM_U) {
-            R av[GM_U][8];
+            double av[GM_U][8];   // widened once at load
             double bv[GM_U][2];
 #pragma unroll
             for (int u = 0; u < GM_U; ++u) {
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
 #pragma unroll
                 for (int mt = 0; mt < 8; ++mt) {
                     const int i = mt * 16 + li;
-                    av[u][mt] = (mt < a.MT && ok && i < nbx) ? xrow[i] : (R)0;
+                    av[u][mt] = (mt < a.MT && ok && i < nbx) ? (double)xrow[i] : 0.0;
                 }
                 const R *yrow = reinterpret_cast<const R *>(a.Y + r * a.ldy);
                 double2 sc = make_double2(1.0, 0.0);
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
                         for (int t = 0; t < 2; ++t)
                             if (g + t * a.G < a.NT)
                                 acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                    (double)av[u][mt], bv[u][t], acc[mt][t], 0, 0, 0);
+                                    av[u][mt], bv[u][t], acc[mt][t], 0, 0, 0);
                     }
                 }
         }
@@ -604,48 +604,93 @@ __global__ __launch_bounds__(256) void coef_prep_kernel(UpdArgs<T> a, T *coef) {
     }
 }
 
-template <typename T, int WO>
-__global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= a.n) return;
-    T acc[WO];
-#pragma unroll
-    for (int c = 0; c < WO; ++c) acc[c] = czero<T>();
-    const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
-    const T *__restrict__ coef = a.coef;
-    int base = 0;
-    for (int t = 0; t < a.nterms; ++t) {
-        const T *in = a.t[t].in + r * a.t[t].ld + a.t[t].col;
-        const int w = a.t[t].w;
-        const T rs = a.t[t].rowscale ? a.t[t].rowscale[r] : from_d<T>(make_double2(1.0, 0.0));
-        const bool scale = a.t[t].rowscale != nullptr;
-        for (int j = 0; j < w; ++j) {
-            T x = in[j];
-            if (scale) x = cmul(rs, x);
-            const T *mrow = coef + (base + j) * a.wout;
-#pragma unroll
-            for (int c = 0; c < WO; ++c)
-                if (c < a.wout) cfma(acc[c], x, mrow[c]);
-        }
-        base += w;
+// One wavefront per 64-row tile.  Input columns are staged through LDS in
+// chunks of CH with coalesced loads (consecutive lanes read consecutive
+// entries of a row); each lane then owns one row of the tile, reads it from
+// LDS and accumulates all wout outputs in registers with coefficients that are
+// uniform across the wavefront (scalar loads).  Outputs leave through the
+// same LDS tile, again as coalesced row segments.
+template <typename T, int WO, int CH>
+__global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a, const T *__restrict__ coef) {
+    extern __shared__ double2 sh_upd_raw[];
+    constexpr int LDT = CH + 1;
+    T *tile = reinterpret_cast<T *>(sh_upd_raw);          // 64 x LDT
+    T *sM = tile + 64 * LDT;                               // wtot x WO (row-major)
+    const int lane = threadIdx.x;
+    for (int e = lane; e < a.wtot * WO; e += 64) {
+        const int j = e / WO, c = e - j * WO;
+        sM[e] = (c < a.wout) ? coef[j * a.wout + c] : czero<T>();
     }
-    T *orow = a.out + r * a.ldo;
-    if (use_beta) {
-        const T beta = from_d<T>(a.beta);
+    const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
+    const T beta = from_d<T>(a.beta);
+    const int jl = lane & (CH - 1), rl = lane / CH;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < a.n; r0 += (int64_t)gridDim.x * 64) {
+        const int64_t r = r0 + lane;
+        const int nrow = (int)min((int64_t)64, a.n - r0);
+        T acc[WO];
 #pragma unroll
-        for (int c = 0; c < WO; ++c) {
-            if (c < a.wout) {
-                const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
-                cfma(acc[c], beta, orow[oc]);
+        for (int c = 0; c < WO; ++c) acc[c] = czero<T>();
+        int base = 0;
+        for (int t = 0; t < a.nterms; ++t) {
+            const T *in = a.t[t].in + a.t[t].col;
+            const int ld = a.t[t].ld, w = a.t[t].w;
+            const bool scale = a.t[t].rowscale != nullptr;
+            const T rs = (scale && r < a.n) ? a.t[t].rowscale[r] : from_d<T>(make_double2(1.0, 0.0));
+            for (int j0 = 0; j0 < w; j0 += CH) {
+                const int cw = min(CH, w - j0);
+                // coalesced staging: CH consecutive lanes read CH consecutive entries of a row
+                T v[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int rr = rl + (64 / CH) * i;
+                    v[i] = (jl < cw && rr < nrow) ? in[(r0 + rr) * ld + j0 + jl] : czero<T>();
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < CH; ++i) tile[(rl + (64 / CH) * i) * LDT + jl] = v[i];
+                __syncthreads();
+                // each lane owns one row of the tile
+                T x[CH];
+#pragma unroll
+                for (int jj = 0; jj < CH; ++jj) {
+                    x[jj] = tile[lane * LDT + jj];
+                    if (scale) x[jj] = cmul(rs, x[jj]);
+                }
+                const T *mrow = sM + (base + j0) * WO;
+#pragma unroll
+                for (int jj = 0; jj < CH; ++jj) {
+                    if (jj < cw) {
+#pragma unroll
+                        for (int c = 0; c < WO; ++c) cfma(acc[c], x[jj], mrow[jj * WO + c]);
+                    }
+                }
+            }
+            base += w;
+        }
+        // write back through the tile, CH output columns at a time
+#pragma unroll
+        for (int c0 = 0; c0 < WO; c0 += CH) {
+            if (c0 < a.wout) {
+                const int cw = min(CH, a.wout - c0);
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < CH; ++c) tile[lane * LDT + c] = acc[c0 + c];
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const int rr = rl + (64 / CH) * i;
+                    if (jl < cw && rr < nrow) {
+                        const int c = c0 + jl;
+                        const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+                        T o = tile[rr * LDT + jl];
+                        T *dst = a.out + (r0 + rr) * a.ldo + oc;
+                        if (use_beta) cfma(o, beta, *dst);
+                        *dst = o;
+                    }
+                }
             }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < WO; ++c) {
-        if (c < a.wout) {
-            const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
-            orow[oc] = acc[c];
-        }
+        __syncthreads();
     }
 }
 
@@ -668,15 +713,19 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     a.coef = static_cast<const T *>(coef);
     hipLaunchKernelGGL((coef_prep_kernel<T>), dim3(1), dim3(256), 0, st, a, static_cast<T *>(coef));
     GPLHR_HIP_CHECK(hipGetLastError());
-    const int grid = (int)((n + 255) / 256);
-    if (wout <= 8)
-        hipLaunchKernelGGL((update_kernel<T, 8>), dim3(grid), dim3(256), 0, st, a);
-    else if (wout <= 16)
-        hipLaunchKernelGGL((update_kernel<T, 16>), dim3(grid), dim3(256), 0, st, a);
-    else if (wout <= 32)
-        hipLaunchKernelGGL((update_kernel<T, 32>), dim3(grid), dim3(256), 0, st, a);
+    const int grid = (int)std::min<int64_t>((n + 63) / 64, 8192);
+    constexpr int CH = (sizeof(T) == 16) ? 8 : 16;
+    const int wo = wout <= 8 ? 8 : wout <= 16 ? 16 : wout <= 32 ? 32 : 48;
+    const size_t shmem = sizeof(T) * ((size_t)64 * (CH + 1) + (size_t)wtot * wo);
+    if (shmem > 64 * 1024) throw Error(-1, "update: coefficient block exceeds LDS");
+    if (wo == 8)
+        hipLaunchKernelGGL((update_kernel<T, 8, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+    else if (wo == 16)
+        hipLaunchKernelGGL((update_kernel<T, 16, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+    else if (wo == 32)
+        hipLaunchKernelGGL((update_kernel<T, 32, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
     else
-        hipLaunchKernelGGL((update_kernel<T, 48>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((update_kernel<T, 48, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
