@@ -28,6 +28,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM-side bytes per launch of the complex64 SpMM on the 160^3 operator with a
+# 16-wide block: rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), the
+# scales being what the same counters read for a 256 MiB device copy.  Valid
+# for the current spmm_kernel; re-measure after any change to it.
+SPMM_C64_160_B16_TRAFFIC = 1.964e9 + 0.524e9
 METRIC = "time to k eigenpairs @1e-10 rel. residual, mixed vs FP64; SpMM HBM GB/s"
 
 
@@ -127,6 +132,8 @@ def main():
     ap.add_argument("--scale", type=int, default=None, help="override n of the default workload")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the SpMM bandwidth measurement on the 160^3 operator (for profiling)")
+    ap.add_argument("--named-only", action="store_true",
+                    help="only the per-iteration timing of the named stencil workloads (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -148,6 +155,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"spmm_160cube_b16": res, "copy_bytes_each_way": x.numel() * 8}), flush=True)
+        return
+
+    if args.named_only:
+        named = {"c2_64cube_fp64_vs_c3_mixed": named_iteration_times(G, torch, "c2", None, 10, ["fp64", "mixed"]),
+                 "c5_160cube": named_iteration_times(G, torch, "c5", None, 3, ["mixed", "fp64"])}
+        print(json.dumps({"named_workloads": named}), flush=True)
         return
 
     p = problems.config("d1m", args.scale)
@@ -227,7 +240,7 @@ def main():
                   "eig_rel_diff_vs_fp64": mixed_vs_fp64},
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
                      "kernel": "spmm_kernel<float2,2> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
                      "bytes_per_launch": sp64["bytes"], "ms_per_launch": sp64["ms"]},
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],
