@@ -82,7 +82,10 @@ typedef struct {
 } gplhr_precond;
 
 enum { GPLHR_FP64 = 0, GPLHR_MIXED = 1 };
-enum { GPLHR_P_THICK = 0, GPLHR_P_NONE = 2 };
+/* Additional search directions P (Section 3.4): thick restart P = Z Ybar_R(:, b+1:2b)
+ * (eq. P1, the paper's default), the previous V (with the projections of step 22
+ * this spans the same space as the LOBPCG-style eq. P_lobpcg), or none. */
+enum { GPLHR_P_THICK = 0, GPLHR_P_LOBPCG = 1, GPLHR_P_NONE = 2 };
 
 typedef struct {
     int precision;      /* GPLHR_FP64: every block in complex128.
@@ -97,7 +100,8 @@ typedef struct {
                            pairs has ||A x - lambda B x|| / ||A x|| <= tol       */
     int max_iter;       /* iteration budget of gplhr_iterate when its max_iter<=0 */
     int arnoldi_m;      /* m of Algorithms 1-2: number of S blocks (>= 1)        */
-    int p_mode;         /* GPLHR_P_THICK (eq. P1, default) or GPLHR_P_NONE       */
+    int p_mode;         /* GPLHR_P_THICK (eq. P1, default), GPLHR_P_LOBPCG or
+                           GPLHR_P_NONE                                          */
     const void *V0;     /* device n-by-block complex128 row-major (ld = block),
                            or NULL: a seeded complex normal block               */
     uint64_t seed;      /* seed of the NULL-V0 generator                         */
@@ -107,10 +111,23 @@ typedef struct {
                            a 10% improvement of the largest residual              */
     int timing;         /* 1: time every kernel class with HIP events (adds a
                            small overhead); read with gplhr_get_stats            */
+    int proj_before_T;  /* 1 (default): apply (I - QQ^H) (B = I: (I - VV^H))
+                           before T as in eq. prec_gen; 0: omit it (the variant
+                           compared in Table 3)                                  */
+    int locking;        /* 1: soft locking (the remarks after Algorithm 2): once
+                           the q leading Rayleigh-Ritz pairs meet tol (q never
+                           decreases, q < block), V and Q keep all columns but
+                           W, S_l and P are built for the a = block - q trailing
+                           columns from the trailing a-by-a blocks of M_A, M_B,
+                           and m grows to min(floor(arnoldi_m block / a), m_max)
+                           so that the trial subspace keeps its size; 0 (default)
+                           disables it                                           */
+    int m_max;          /* upper bound of the adaptive m under locking (>= 1)    */
 } gplhr_options;
 
 /* Fill *opt with defaults: FP64, tol 1e-10, max_iter 500, arnoldi_m 1, thick P,
- * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0. */
+ * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0,
+ * proj_before_T 1, locking 0, m_max 20. */
 void gplhr_default_options(gplhr_options *opt);
 
 /* Set up the operator C = A - sigma B on the union sparsity pattern, its
@@ -194,6 +211,8 @@ typedef struct {
     double max_rel_resid;      /* last convergence check                    */
     int n_converged;
     int phase;                 /* 0 = complex64 phase, 1 = complex128        */
+    int locked;                /* q: leading columns locked (soft locking)  */
+    int arnoldi_m;             /* m used by the last iteration              */
 } gplhr_stats;
 
 gplhr_status gplhr_get_stats(gplhr_t h, gplhr_stats *out);

@@ -205,6 +205,7 @@ class GplhrResult:
     converged: bool
     history: list = field(default_factory=list)   # max rho over the k leading pairs, per check
     lam_history: list = field(default_factory=list)
+    lock_history: list = field(default_factory=list)  # (q, m) used by each iteration
     trace: list = field(default_factory=list)     # optional per-iteration internals
 
     @property
@@ -215,6 +216,7 @@ class GplhrResult:
 
 def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
           m: int = 1, tol: float = 1e-10, maxit: int = 500, p_mode: str = "thick",
+          proj_before_T: bool = True, locking: bool = False, m_max: int = 20,
           keep_trace: bool = False, callback: Optional[Callable] = None) -> GplhrResult:
     """Algorithm 2 (GPLHR, Schur-vector form).
 
@@ -223,8 +225,19 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
     k        number of wanted eigenpairs; the block width b = V0.shape[1] >= k.
     precond  callable applying T ~ (A - sigma B)^{-1} to a block.
     m        Krylov-Arnoldi depth (number of S blocks).
-    p_mode   "thick": P = Z Ybar_R(:, b+1:2b) (eq. P1, step 28);
-             "none":  no P block (trial space of eq. trial_partial).
+    p_mode   "thick":  P = Z Ybar_R(:, b+1:2b) (eq. P1, step 28);
+             "lobpcg": P = the previous V (eq. P_lobpcg: V^(i) - V^(i-1) C_V spans,
+                       together with V^(i), the same space; the projections of
+                       step 22 then turn it into that direction);
+             "none":   no P block (trial space of eq. trial_partial).
+    proj_before_T  apply (I - QQ^*) (B = I: (I - VV^*)) before T, as in eqs.
+             prec_gen / prec; False gives the variant of Table 3 without it.
+    locking  soft locking (the remarks after Algorithm 2): once the q leading
+             Rayleigh-Ritz pairs have converged (contiguously; q never decreases
+             and stays below b), V and Q keep all b columns but W, S_l and P
+             are built for the a = b - q trailing columns only (the S recursion
+             uses the trailing a-by-a blocks of M_A, M_B; P keeps its first a
+             columns), and m <- min(floor(m0 b / (b - q)), m_max).
     """
     A = sp.csr_matrix(A)
     std = B is None
@@ -247,7 +260,9 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
     Q = Q @ YL
     MA, MB, _ = q_free_factors(RA, RB)
 
-    history, lam_history, trace = [], [], []
+    history, lam_history, lock_history, trace = [], [], [], []
+    m0 = m
+    q = 0
     it = 0
     while True:
         lam, X, rho, _ = ritz_pairs(A, None if std else Bm, V, sigma)
@@ -258,28 +273,41 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
         if np.max(rho[:k]) <= tol or it >= maxit:
             break
         it += 1
+        if locking:
+            nconv = 0
+            while nconv < b and rho[nconv] <= tol:
+                nconv += 1
+            q = max(q, min(nconv, b - 1))
+            m = min((m0 * b) // (b - q), m_max)
+        a = b - q
+        lock_history.append((q, m))
+        MAa, MBa = MA[q:, q:], MB[q:, q:]
+        if P is not None:
+            P = P[:, :a]
 
         def proj_V(X):
             return X - V @ (V.conj().T @ X)
 
         def proj_left(X):   # I - QQ^* for B != I, I - VV^* for B = I
+            if not proj_before_T:
+                return X
             Y = V if std else Q
             return X - Y @ (Y.conj().T @ X)
 
-        # steps 6-10: projected preconditioned residual
+        # steps 6-10: projected preconditioned residual (active columns q..b-1)
         if not std:
             WA = A @ V - Q @ RA
             WB = Bm @ V - Q @ RB
-            W = proj_V(precond(proj_left(WA @ MB - WB @ MA)))
+            W = proj_V(precond(proj_left((WA @ MB - WB @ MA)[:, q:])))
         else:
-            W = proj_V(precond(proj_left(A @ V @ MB - V @ MA)))
+            W = proj_V(precond(proj_left((A @ V @ MB - V @ MA)[:, q:])))
         # step 12
         W = orth(W)
         S_prev = W
         S = np.zeros((V.shape[0], 0), dtype=complex)
         # steps 13-21: Krylov-Arnoldi blocks
         for _ in range(m):
-            Sl = proj_V(precond(proj_left(A @ S_prev @ MB - Bx(S_prev) @ MA)))
+            Sl = proj_V(precond(proj_left(A @ S_prev @ MBa - Bx(S_prev) @ MAa)))
             Sl = Sl - W @ (W.conj().T @ Sl)
             Sl = Sl - S @ (S.conj().T @ Sl)
             Sl = orth(Sl)
@@ -309,10 +337,16 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
         RA = RAb[:b, :b]
         RB = RBb[:b, :b]
         # steps 27-28: V = Z Y_R (= V Y_V + W Y_W + S Y_S + P Y_P), Q = U Y_L
+        V_old = V
         V = Z @ YR
         Q = U @ YL
-        # step 29: thick restart
-        P = Z @ YRb[:, b:2 * b] if p_mode == "thick" else None
+        # step 29: thick restart (or the LOBPCG-style direction)
+        if p_mode == "thick":
+            P = Z @ YRb[:, b:b + a]
+        elif p_mode == "lobpcg":
+            P = V_old[:, q:]
+        else:
+            P = None
         # steps 30-31
         MA, MB, _ = q_free_factors(RA, RB)
         if keep_trace:
@@ -321,7 +355,8 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
 
     return GplhrResult(V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB, lam=lam, X=X, rho=rho,
                        iterations=it, converged=bool(np.max(rho[:k]) <= tol),
-                       history=history, lam_history=lam_history, trace=trace)
+                       history=history, lam_history=lam_history,
+                       lock_history=lock_history, trace=trace)
 
 
 def solve_problem(problem, tol: Optional[float] = None, maxit: int = 500, **kw) -> GplhrResult:

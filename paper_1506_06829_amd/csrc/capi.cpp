@@ -53,6 +53,9 @@ void gplhr_default_options(gplhr_options *opt) {
     opt->switch_tol = 1e-5;
     opt->stall_window = 20;
     opt->timing = 0;
+    opt->proj_before_T = 1;
+    opt->locking = 0;
+    opt->m_max = 20;
 }
 
 gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B, double sigma_re,
@@ -281,6 +284,8 @@ gplhr_status gplhr_get_stats(gplhr_t h, gplhr_stats *out) {
         out->max_rel_resid = c.max_rho;
         out->n_converged = c.nconv;
         out->phase = c.phase;
+        out->locked = c.q;
+        out->arnoldi_m = c.m_cur;
         return 0;
     });
 }

@@ -47,12 +47,15 @@ struct Ctx {
     gplhr_options opt{};
     gplhr_precond pre{};
     int64_t n = 0;
-    int k = 0, b = 0, m = 1, smax = 0;
+    // m: Krylov-Arnoldi depth requested; m_cur: depth of the current
+    // iteration (grows under locking); q: locked leading columns; pw: width of
+    // the P block kept at columns smax - b .. between iterations (0: none)
+    int k = 0, b = 0, m = 1, smax = 0, m_cur = 1, q = 0, pw = 0;
     cd sigma;
     BKind bk = B_IDENT;
     bool mixed = false, xcd_remap = false;
     int phase = 1;
-    bool haveP = false, converged = false, checked = false;
+    bool converged = false, checked = false;
 
     // operator
     int32_t *c_rp = nullptr, *c_ci = nullptr;
@@ -86,7 +89,7 @@ struct Ctx {
     std::vector<cd> lam_h;
     std::vector<double> rho_h, resid_h, history;
     double max_rho = INFINITY;
-    int nconv = 0;
+    int nconv = 0, nlead = 0;   // leading pairs meeting tol: of the k wanted, of all b
 
     // counters
     int64_t n_iter = 0, n_iter64 = 0, n_spmm = 0, n_prec = 0, n_breakdown = 0;
@@ -119,11 +122,12 @@ struct Ctx {
     template <typename T>
     void cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2);
     template <typename T>
-    void spmm_c(const T *X, int ldx, T *Y, int ldy, int mode, const T *Rhs, int ldr);
+    void spmm_c(const T *X, int ldx, T *Y, int ldy, int w, int mode, const T *Rhs, int ldr);
     template <typename T>
-    void spmm_b(const T *X, int ldx, T *Y, int ldy);
-    template <typename T> void apply_T(T *dest, int ldd, int dcol);
-    template <typename T> void srr_and_update(int s_cur, int nkeep_req);
+    void spmm_b(const T *X, int ldx, T *Y, int ldy, int w);
+    template <typename T> void apply_T(T *dest, int ldd, int dcol, int w);
+    template <typename T> void srr_and_update(int s_cur, int p_cols);
+    void update_locking();
     template <typename T> void init_from_Z(int w0);
     template <typename T> void iterate_once();
     template <typename T> void refresh_products();

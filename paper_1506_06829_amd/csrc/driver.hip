@@ -2,11 +2,15 @@
 // stream, with the block work in kernels.hip and the small projected step in
 // small_dense.cpp.  Exposed through the C ABI in capi.cpp.
 //
-// Trial basis layout (n-by-smax, row-major, ld = smax, s = (m+3) b):
-//   Z = [ V | W | S_1 .. S_m | P ]   with V at column 0, W at b, S_l at (l+1) b,
-//   P at (m+2) b.  CZ = C Z with C = A - sigma B is kept alongside Z (fresh
-//   sparse products for W and S_l, the same linear combinations as Z for V and
-//   P), BZ likewise when B is a general sparse matrix.  U = [ Q | Qhat ].
+// Trial basis layout (n-by-smax, row-major, ld = smax, smax = (m+3) b):
+//   Z = [ V | W | S_1 .. S_mc | P ]   with V at column 0 (b columns) and, for
+//   the a = b - q active columns (q locked, 0 without locking), W at b, S_l at
+//   b + l a and P at pos = b + (mc+1) a, mc the depth of the iteration.  Since
+//   mc a <= m b, everything fits in smax columns.  Between iterations P is kept
+//   at smax - b (= pos when q = 0) and moved to pos when the layout shrinks.
+//   CZ = C Z with C = A - sigma B is kept alongside Z (fresh sparse products for
+//   W and S_l, the same linear combinations as Z for V and P), BZ likewise when
+//   B is a general sparse matrix.  U = [ Q | Qhat ].
 #include "driver.h"
 
 #include <algorithm>
@@ -160,47 +164,47 @@ void Ctx::cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2) {
 }
 
 template <typename T>
-void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int mode, const T *Rhs, int ldr) {
+void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int wc, int mode, const T *Rhs, int ldr) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, b, mode, Rhs, ldr, w.dw, xcd_remap);
+    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, xcd_remap);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
-                  (double)n * b * sizeof(T) * (mode == 0 ? 2 : 3);
+                  (double)n * wc * sizeof(T) * (mode == 0 ? 2 : 3);
 }
 
 template <typename T>
-void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy) {
+void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy, int wc) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, b, 0, nullptr, 0, nullptr, xcd_remap);
+    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, wc, 0, nullptr, 0, nullptr, xcd_remap);
     tend(T_SPMM);
     ++n_spmm;
-    spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * b * sizeof(T);
+    spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * wc * sizeof(T);
 }
 
-// dest(:, dcol:dcol+b) = T R  (R = Work.R, ld b)
+// dest(:, dcol:dcol+wc) = T R  (R = Work.R, ld b, wc <= b columns)
 template <typename T>
-void Ctx::apply_T(T *dest, int ldd, int dcol) {
+void Ctx::apply_T(T *dest, int ldd, int dcol, int wc) {
     Work<T> &w = W<T>();
     ++n_prec;
     if (pre.kind == GPLHR_PRECOND_NONE) {
-        launch_scale_rows<T>(st, n, b, w.R, b, nullptr, dest + dcol, ldd);
+        launch_scale_rows<T>(st, n, wc, w.R, b, nullptr, dest + dcol, ldd);
     } else if (pre.kind == GPLHR_PRECOND_DIAG) {
-        launch_scale_rows<T>(st, n, b, w.R, b, w.dinv, dest + dcol, ldd);
+        launch_scale_rows<T>(st, n, wc, w.R, b, w.dinv, dest + dcol, ldd);
     } else {
         // w_1 = omega D^{-1} r; w_{t+1} = w_t + omega D^{-1} (r - C w_t)
         if (pre.sweeps == 1) {
-            launch_scale_rows<T>(st, n, b, w.R, b, w.dw, dest + dcol, ldd);
+            launch_scale_rows<T>(st, n, wc, w.R, b, w.dw, dest + dcol, ldd);
             return;
         }
-        launch_scale_rows<T>(st, n, b, w.R, b, w.dw, w.J1, b);
+        launch_scale_rows<T>(st, n, wc, w.R, b, w.dw, w.J1, b);
         T *cur = w.J1;
         for (int t = 1; t < pre.sweeps; ++t) {
             const bool last = (t == pre.sweeps - 1);
             T *o = last ? dest + dcol : (cur == w.J1 ? w.J2 : w.J1);
-            spmm_c<T>(cur, b, o, last ? ldd : b, 1, w.R, b);
+            spmm_c<T>(cur, b, o, last ? ldd : b, wc, 1, w.R, b);
             cur = o;
         }
     }
@@ -209,8 +213,9 @@ void Ctx::apply_T(T *dest, int ldd, int dcol) {
 // ---------------------------------------------------------------------------
 // projected pencil -> ordered Schur form -> basis update
 // ---------------------------------------------------------------------------
+// p_cols: width of the P block the update should produce (0: none).
 template <typename T>
-void Ctx::srr_and_update(int s_cur, int nkeep_req) {
+void Ctx::srr_and_update(int s_cur, int p_cols) {
     Work<T> &w = W<T>();
     const int ld = smax;
     const T *bsrc = (bk == B_SPARSE) ? w.BZ : w.Z;
@@ -237,17 +242,28 @@ void Ctx::srr_and_update(int s_cur, int nkeep_req) {
     for (const cd &v : K.a)
         if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
             throw Error(-6, "non-finite entries in the projected pencil");
-    const int nkeep = std::min(nkeep_req, s_cur);
+    const bool lobpcg = (opt.p_mode == GPLHR_P_LOBPCG);
+    const bool thick = (opt.p_mode == GPLHR_P_THICK);
+    const int nkeep = std::min(thick ? b + p_cols : b, s_cur);
     small::SrrResult r;
     if (!small::harmonic_srr(K, Gm, sigma, b, nkeep, r))
         throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
                         "(Proposition 3.1)");
     small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     RA = r.RA; RB = r.RB; MA = r.MA; MB = r.MB;
-    // coefficients: [Y_R | Y_P] (s_cur x ncols), Y_L (s_cur x b), M1 = M_B, M2 = sigma M_B - M_A
-    const int nc = r.ncols;
+    // coefficients: [Y_R | Y_P] (s_cur x nc), Y_L (s_cur x b), M1 = M_B, M2 = sigma M_B - M_A.
+    // Y_P is Ybar_R(:, b+1:b+p) for the thick restart (step 29), or, for the
+    // LOBPCG-style direction, the unit vectors that pick the active columns of
+    // the current V, so that one row-local update produces V_new and P = V_old.
+    int nc = r.ncols;
     size_t off = 0;
     std::memcpy(hpin + off, r.YR.data(), (size_t)s_cur * nc * sizeof(cd));
+    if (lobpcg && p_cols > 0 && s_cur > b) {
+        cd *ext = reinterpret_cast<cd *>(hpin) + (size_t)s_cur * nc;
+        std::fill(ext, ext + (size_t)s_cur * p_cols, cd(0.0, 0.0));
+        for (int j = 0; j < p_cols; ++j) ext[(size_t)j * s_cur + (b - p_cols) + j] = cd(1.0, 0.0);
+        nc += p_cols;
+    }
     off += (size_t)s_cur * nc;
     std::memcpy(hpin + off, r.YL.data(), (size_t)s_cur * b * sizeof(cd));
     off += (size_t)s_cur * b;
@@ -262,8 +278,9 @@ void Ctx::srr_and_update(int s_cur, int nkeep_req) {
     GPLHR_HIP_CHECK(hipMemcpyAsync(coefL, hpin + (size_t)s_cur * nc, (size_t)s_cur * b * sizeof(double2), hipMemcpyHostToDevice, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(M1, hpin + (size_t)s_cur * (nc + b), (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(M2, hpin + (size_t)s_cur * (nc + b) + (size_t)b * b, (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
-    // a10: V = Z Y_R, P = Z Ybar_R(:, b+1:2b) (and the same for CZ, BZ); Q = U Y_L
-    const int offP = (m + 2) * b;
+    // a10: V = Z Y_R, P = Z Y_P (and the same for CZ, BZ); Q = U Y_L.  P lands
+    // at its between-iterations slot smax - b.
+    const int offP = smax - b;
     UpdTerm<T> t;
     t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
     t.in = w.Z;
@@ -278,7 +295,7 @@ void Ctx::srr_and_update(int s_cur, int nkeep_req) {
     update<T>(w.U, ld, b, 0, b, 0, false, 1, &t);
     // The host writes the pinned staging buffer again only after a stream
     // synchronisation, so the uploads above cannot be overtaken.
-    haveP = (nc >= 2 * b);
+    pw = nc - b;
 }
 
 // Steps 1-4 of Algorithm 2 from Z(:, 0:w0) (V0, or [V P] when restarting in
@@ -289,53 +306,69 @@ void Ctx::init_from_Z(int w0) {
     const int ld = smax;
     cholqr<T>(w.Z, ld, 0, w0, 2, nullptr, nullptr);
     for (int c = 0; c < w0; c += b) {
-        spmm_c<T>(w.Z + c, ld, w.CZ + c, ld, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(w.Z + c, ld, w.BZ + c, ld);
+        const int wc = std::min(b, w0 - c);
+        spmm_c<T>(w.Z + c, ld, w.CZ + c, ld, wc, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(w.Z + c, ld, w.BZ + c, ld, wc);
     }
     launch_scale_rows<T>(st, n, w0, w.CZ, ld, nullptr, w.U, ld);
     cholqr<T>(w.U, ld, 0, w0, 2, nullptr, nullptr);
-    const int nkeep = (w0 >= 2 * b && opt.p_mode == GPLHR_P_THICK) ? 2 * b : b;
-    srr_and_update<T>(w0, nkeep);
+    srr_and_update<T>(w0, (w0 > b && opt.p_mode != GPLHR_P_NONE) ? b - q : 0);
 }
 
-// One GPLHR iteration (Algorithm 2, steps 6-31).
+// One GPLHR iteration (Algorithm 2, steps 6-31), with soft locking of the q
+// leading columns when enabled.
 template <typename T>
 void Ctx::iterate_once() {
     Work<T> &w = W<T>();
     const int ld = smax;
-    const int offW = b, offP = (m + 2) * b;
-    const int s_cur = haveP ? smax : (m + 2) * b;
+    const int a = b - q;                       // active columns
+    const int offW = b;
+    const int pos = b + (m_cur + 1) * a;       // P slot of this iteration
+    const int offPs = smax - b;                // P slot between iterations
+    const int pa = std::min(pw, a);            // P columns used (first ones kept)
+    const int s_cur = pos + pa;
     T *Z = w.Z, *CZ = w.CZ, *BZ = w.BZ, *U = w.U;
     // left projector basis: Q when B != I, V when B = I (steps 8/10, 15/17)
     const T *Lb = (bk == B_IDENT) ? Z : U;
     const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
 
-    // src block -> new block at dst:
-    //   R = (A - sigma B) X M_B + B X (sigma M_B - M_A)  (= A X M_B - B X M_A)
+    // src block (width ws) -> new block of width a at dst:
+    //   R = (A - sigma B) X M_B(., q:) + B X (sigma M_B - M_A)(., q:)   (moff selects
+    //   the columns q: of M for X = V and the trailing a-by-a block for X = S_l)
     //   R <- (I - Q Q^H) R;  Y = T R;  Y <- (I - [V W S_<l] [.]^H) Y (two passes)
     //   Y <- orth(Y);  C Y (and B Y)
-    auto build = [&](int src, int dst) {
+    auto build = [&](int src, int ws, int moff, int dst) {
         UpdTerm<T> t[2];
-        t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = b; t[0].M = M1; t[0].ldm = b;
-        t[1].in = (bk == B_SPARSE) ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = b;
-        t[1].M = M2; t[1].ldm = b; t[1].rowscale = bsc;
-        update<T>(w.R, b, b, 0, b, 0, false, 2, t);
-        project<T>(w.R, b, 0, b, Lb, ld, 0, b);
-        apply_T<T>(Z, ld, dst);
-        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, dst, b, Z, ld, 0, dst);
-        cholqr<T>(Z, ld, dst, b, 2, nullptr, nullptr);
-        spmm_c<T>(Z + dst, ld, CZ + dst, ld, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(Z + dst, ld, BZ + dst, ld);
+        t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = ws; t[0].M = M1 + moff; t[0].ldm = b;
+        t[1].in = (bk == B_SPARSE) ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = ws;
+        t[1].M = M2 + moff; t[1].ldm = b; t[1].rowscale = bsc;
+        update<T>(w.R, b, a, 0, a, 0, false, 2, t);
+        if (opt.proj_before_T) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
+        apply_T<T>(Z, ld, dst, a);
+        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, dst, a, Z, ld, 0, dst);
+        cholqr<T>(Z, ld, dst, a, 2, nullptr, nullptr);
+        spmm_c<T>(Z + dst, ld, CZ + dst, ld, a, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(Z + dst, ld, BZ + dst, ld, a);
     };
-    build(0, offW);                                   // W (steps 6-12)
-    for (int l = 1; l <= m; ++l) build(offW + (l - 1) * b, offW + l * b);   // S_l (steps 13-21)
+    build(0, b, q * b, offW);                                        // W (steps 6-12)
+    for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
+        build(offW + (l - 1) * a, a, q + q * b, offW + l * a);
 
     // step 22: P <- orth(P - [V W S][V W S]^H P), mirrored onto C P (and B P)
-    if (haveP) {
+    if (pa > 0) {
+        T *bz = (bk == B_SPARSE) ? BZ : nullptr;
+        if (pos != offPs) {
+            // the layout is narrower than the kept one: move P next to S_mc
+            // (row-local, so overlapping column ranges are safe)
+            UpdTerm<T> t;
+            t.ld = ld; t.col = offPs; t.w = pa; t.M = eye; t.ldm = EYE_N;
+            t.in = Z;  update<T>(Z, ld, pa, pos, pa, 0, false, 1, &t);
+            t.in = CZ; update<T>(CZ, ld, pa, pos, pa, 0, false, 1, &t);
+            if (bz) { t.in = bz; update<T>(bz, ld, pa, pos, pa, 0, false, 1, &t); }
+        }
         for (int pass = 0; pass < 2; ++pass)
-            project<T>(Z, ld, offP, b, Z, ld, 0, offP, CZ, CZ, bk == B_SPARSE ? BZ : nullptr,
-                       bk == B_SPARSE ? BZ : nullptr);
-        cholqr<T>(Z, ld, offP, b, 2, CZ, bk == B_SPARSE ? BZ : nullptr);
+            project<T>(Z, ld, pos, pa, Z, ld, 0, pos, CZ, CZ, bz, bz);
+        cholqr<T>(Z, ld, pos, pa, 2, CZ, bz);
     }
     // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])]
     const int wq = s_cur - b;
@@ -350,7 +383,7 @@ void Ctx::iterate_once() {
     project<T>(U, ld, b, wq, U, ld, 0, b);
     cholqr<T>(U, ld, b, wq, 2, nullptr, nullptr);
     // steps 25-31
-    srr_and_update<T>(s_cur, opt.p_mode == GPLHR_P_THICK ? 2 * b : b);
+    srr_and_update<T>(s_cur, opt.p_mode == GPLHR_P_NONE ? 0 : a);
     ++n_iter;
     if (sizeof(T) == sizeof(double2)) ++n_iter64;
 }
@@ -360,13 +393,21 @@ void Ctx::iterate_once() {
 template <typename T>
 void Ctx::refresh_products() {
     Work<T> &w = W<T>();
-    const int ld = smax, offP = (m + 2) * b;
-    spmm_c<T>(w.Z, ld, w.CZ, ld, 0, nullptr, 0);
-    if (bk == B_SPARSE) spmm_b<T>(w.Z, ld, w.BZ, ld);
-    if (haveP) {
-        spmm_c<T>(w.Z + offP, ld, w.CZ + offP, ld, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(w.Z + offP, ld, w.BZ + offP, ld);
+    const int ld = smax, offP = smax - b;
+    spmm_c<T>(w.Z, ld, w.CZ, ld, b, 0, nullptr, 0);
+    if (bk == B_SPARSE) spmm_b<T>(w.Z, ld, w.BZ, ld, b);
+    if (pw > 0) {
+        spmm_c<T>(w.Z + offP, ld, w.CZ + offP, ld, pw, 0, nullptr, 0);
+        if (bk == B_SPARSE) spmm_b<T>(w.Z + offP, ld, w.BZ + offP, ld, pw);
     }
+}
+
+// Soft locking: q <- max(q, min(leading converged pairs, b - 1)) and the
+// Krylov-Arnoldi depth that keeps the trial subspace at its size.
+void Ctx::update_locking() {
+    if (!opt.locking) { m_cur = m; return; }
+    q = std::max(q, std::min(nlead, b - 1));
+    m_cur = std::min((m * b) / (b - q), opt.m_max);
 }
 
 // Rayleigh-Ritz pairs on span(V) and their relative residuals (FP64).
@@ -410,12 +451,15 @@ void Ctx::check() {
     resid_h.assign(b, 0.0);
     max_rho = 0.0;
     nconv = 0;
-    bool lead = true;
+    nlead = 0;
+    bool lead = true, lead_all = true;
     for (int j = 0; j < b; ++j) {
         const cd v = reinterpret_cast<cd *>(hpin)[bb + b + j];
         resid_h[j] = std::sqrt(v.real());
         rho_h[j] = v.imag() > 0 ? std::sqrt(v.real() / v.imag()) : INFINITY;
         if (!std::isfinite(rho_h[j]) && v.imag() > 0) throw Error(-6, "non-finite residual");
+        if (lead_all && rho_h[j] <= opt.tol) ++nlead;
+        else lead_all = false;
         if (j < k) {
             max_rho = std::max(max_rho, rho_h[j]);
             if (lead && rho_h[j] <= opt.tol) ++nconv;
@@ -440,11 +484,14 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     k = k_;
     b = b_;
     m = opt.arnoldi_m;
+    m_cur = m;
     if (n < 1 || n > INT32_MAX - 1) throw Error(-1, "n out of range");
     if (A->nnz < 0 || A->nnz > INT32_MAX) throw Error(-1, "nnz(A) out of range");
     if (k < 1 || b < k) throw Error(-1, "need 1 <= k <= block");
     if (m < 1) throw Error(-1, "arnoldi_m must be >= 1");
-    if (opt.p_mode != GPLHR_P_THICK && opt.p_mode != GPLHR_P_NONE) throw Error(-1, "unsupported p_mode");
+    if (opt.locking && opt.m_max < m) throw Error(-1, "m_max must be >= arnoldi_m");
+    if (opt.p_mode != GPLHR_P_THICK && opt.p_mode != GPLHR_P_LOBPCG && opt.p_mode != GPLHR_P_NONE)
+        throw Error(-1, "unsupported p_mode");
     if (opt.precision != GPLHR_FP64 && opt.precision != GPLHR_MIXED) throw Error(-1, "bad precision");
     smax = (m + 3) * b;
     if ((m + 2) * b > 48 || smax > 64)
@@ -572,12 +619,12 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
 }
 
 void Ctx::switch_to_fp64() {
-    const int offP = (m + 2) * b;
+    const int offP = smax - b;
     launch_c64_to_c128(st, n, b, wf.Z, smax, wd.Z, smax);
     int w0 = b;
-    if (haveP) {
-        launch_c64_to_c128(st, n, b, wf.Z + offP, smax, wd.Z + b, smax);
-        w0 = 2 * b;
+    if (pw > 0) {
+        launch_c64_to_c128(st, n, pw, wf.Z + offP, smax, wd.Z + b, smax);
+        w0 = b + pw;
     }
     phase = 1;
     init_from_Z<double2>(w0);
@@ -613,6 +660,7 @@ int Ctx::run(int max_it) {
             }
         }
         if (done >= max_it) break;
+        update_locking();
         if (phase == 0) iterate_once<float2>(); else iterate_once<double2>();
         checked = false;
         ++done;

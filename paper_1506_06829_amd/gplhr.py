@@ -46,7 +46,8 @@ class _Options(ctypes.Structure):
                 ("arnoldi_m", ctypes.c_int), ("p_mode", ctypes.c_int), ("V0", ctypes.c_void_p),
                 ("seed", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
                 ("switch_tol", ctypes.c_double), ("stall_window", ctypes.c_int),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("proj_before_T", ctypes.c_int),
+                ("locking", ctypes.c_int), ("m_max", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -57,7 +58,8 @@ class _Stats(ctypes.Structure):
                 ("update_ms", ctypes.c_double), ("small_host_ms", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("iterate_ms", ctypes.c_double),
                 ("max_rel_resid", ctypes.c_double), ("n_converged", ctypes.c_int),
-                ("phase", ctypes.c_int)]
+                ("phase", ctypes.c_int), ("locked", ctypes.c_int),
+                ("arnoldi_m", ctypes.c_int)]
 
 
 EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
@@ -153,7 +155,8 @@ class Solver:
                  omega: float = 0.7, precision: str = "fp64", tol: float = 1e-10,
                  max_iter: int = 500, m: int = 1, p_mode: str = "thick",
                  V0: Optional[torch.Tensor] = None, seed: int = 1, timing: bool = False,
-                 switch_tol: float = 1e-5, stall_window: int = 20, stream=None):
+                 switch_tol: float = 1e-5, stall_window: int = 20, stream=None,
+                 proj_before_T: bool = True, locking: bool = False, m_max: int = 20):
         L = lib()
         self.n, self.k = A.n, k
         self.block = block or k
@@ -164,7 +167,7 @@ class Solver:
         opt.tol = tol
         opt.max_iter = max_iter
         opt.arnoldi_m = m
-        opt.p_mode = {"thick": 0, "none": 2}[p_mode]
+        opt.p_mode = {"thick": 0, "lobpcg": 1, "none": 2}[p_mode]
         if V0 is not None:
             assert V0.dtype == torch.complex128 and V0.is_contiguous()
             assert tuple(V0.shape) == (A.n, self.block)
@@ -175,6 +178,9 @@ class Solver:
         opt.switch_tol = switch_tol
         opt.stall_window = stall_window
         opt.timing = 1 if timing else 0
+        opt.proj_before_T = 1 if proj_before_T else 0
+        opt.locking = 1 if locking else 0
+        opt.m_max = m_max
         pre = _Precond(PRECOND[precond], sweeps, omega)
         a = A._c()
         b = B._c() if B is not None else None

@@ -11,6 +11,8 @@
 * Schur-form outputs, the standard-problem R, error paths, and the eigenvalue
   gradient against the dense FP64 reference.
 """
+import functools
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -35,6 +37,44 @@ def test_trajectory_parity_fp64(device, name, scale, its):
     ref = O.solve_problem(p, tol=0.0, maxit=its).lam_history
     for i, (a, b) in enumerate(zip(gpu, ref)):
         assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, (name, scale, i)
+
+
+@pytest.mark.parametrize("variant", [dict(p_mode="lobpcg"), dict(p_mode="none"),
+                                     dict(proj_before_T=False), dict(m=2)])
+def test_trajectory_parity_variants(device, variant):
+    # the ablations of Section 5 (P choices of Table 2, no projector before T
+    # of Table 3) and a deeper Krylov-Arnoldi sequence (m = 2)
+    p = problems.config("c4", 600)
+    its = 5
+    gpu = gpu_trajectory(p, its, precision="fp64", **variant)
+    okw = {"proj_before_T" if k == "proj_before_T" else k: v for k, v in variant.items()}
+    ref = O.solve_problem(p, tol=0.0, maxit=its, **okw).lam_history
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, (variant, i)
+
+
+@pytest.mark.parametrize("seed,p_mode", [(2, "thick"), (0, "lobpcg")])
+def test_locking_trajectory_parity(device, seed, p_mode):
+    # soft locking with adaptive m: locked count, depth and eigenvalues after
+    # every iteration agree with the oracle until convergence
+    n, k = 300, 4
+    A, B = problems.diag_dominant_pencil(n, seed=seed)
+    p = problems.Problem("dd300", A, B, n / 2 + 0.3j, k, k, "diag", tol=1e-11)
+    p.V0 = problems.start_block(n, k, seed=seed)
+    ref = O.solve_problem(p, tol=1e-11, maxit=100, locking=True, p_mode=p_mode)
+    assert ref.converged
+    s, _, _ = gpu_solver(p, tol=1e-11, locking=True, p_mode=p_mode, max_iter=100)
+    lam = s.schur(want_vectors=False)["lam"]
+    assert match_err(lam[:k], ref.lam_history[0]) < FP64_TRAJ_TOL
+    st = 1
+    for i in range(ref.iterations):
+        st, _, _ = s.iterate(1)
+        stats = s.stats()
+        assert (stats["locked"], stats["arnoldi_m"]) == ref.lock_history[i], i
+        lam = s.schur(want_vectors=False)["lam"]
+        assert match_err(lam[:k], ref.lam_history[i + 1]) < FP64_TRAJ_TOL, i
+    s.close()
+    assert st == 0
 
 
 @pytest.mark.parametrize("name,scale,its", [("c2", 12, 4), ("d1", 3000, 4)])
@@ -73,18 +113,24 @@ def test_converged_parity_small(device, precision):
         assert stats["fp64_iterations"] < stats["iterations"]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_converged_parity_full_size(device, precision):
+@functools.lru_cache(maxsize=None)
+def _d1_reference():
+    ref = O.solve_problem(problems.config("d1"), tol=1e-10, maxit=100)
+    assert ref.converged
+    return ref.lam
+
+
+@pytest.mark.parametrize("precision,locking", [("fp64", False), ("mixed", False),
+                                               ("fp64", True), ("mixed", True)])
+def test_converged_parity_full_size(device, precision, locking):
     # n = 262144, k = 10, B = diag U[1,2], diagonal preconditioner
     p = problems.config("d1")
-    s, _, _ = gpu_solver(p, precision=precision, max_iter=100)
+    s, _, _ = gpu_solver(p, precision=precision, max_iter=100, locking=locking)
     st, nconv, res = s.iterate()
     lam = s.schur(want_vectors=False)["lam"]
     s.close()
     assert st == 0 and res <= 1e-10
-    ref = O.solve_problem(p, tol=1e-10, maxit=100)
-    assert ref.converged
-    assert match_err(lam[:p.k], ref.lam[:p.k]) < 1e-10
+    assert match_err(lam[:p.k], _d1_reference()[:p.k]) < 1e-10
 
 
 def test_schur_outputs(device):

@@ -201,8 +201,13 @@ def test_c1_exact_preconditioner_closed_form():
     assert res < 1e-8
 
 
-@pytest.mark.parametrize("seed,std,m", [(0, False, 1), (1, True, 1), (2, False, 2)])
-def test_small_pencils_match_zggev(seed, std, m):
+@pytest.mark.parametrize("seed,std,m,p_mode,proj", [(0, False, 1, "thick", True),
+                                                     (1, True, 1, "thick", True),
+                                                     (2, False, 2, "thick", True),
+                                                     (7, False, 1, "lobpcg", True),
+                                                     (4, True, 1, "none", True),
+                                                     (5, False, 1, "thick", False)])
+def test_small_pencils_match_zggev(seed, std, m, p_mode, proj):
     rng = np.random.default_rng(seed)
     n, k = 40, 3
     A = rand_c(rng, n, n) + 3 * np.eye(n)
@@ -211,10 +216,48 @@ def test_small_pencils_match_zggev(seed, std, m):
     Bm = np.eye(n) if std else B
     C = sp.csr_matrix(A - sigma * Bm)
     r = O.gplhr(sp.csr_matrix(A), None if std else sp.csr_matrix(B), sigma, k, rand_c(rng, n, k),
-                O.make_preconditioner(C, "exact"), m=m, tol=1e-11, maxit=60)
+                O.make_preconditioner(C, "exact"), m=m, tol=1e-11, maxit=60, p_mode=p_mode,
+                proj_before_T=proj)
     assert r.converged
     ref = nearest(sla.eigvals(A, Bm), sigma, k)
     assert match_err(r.lam[:k], ref) < 1e-9
+
+
+def _dd_pencil(n, seed, b):
+    A, B = problems.diag_dominant_pencil(n, seed=seed)
+    As, Bs = A.to_scipy(), B.to_scipy()
+    sigma = n / 2 + 0.3j
+    C = (As - sigma * Bs).tocsr()
+    return As, Bs, sigma, O.make_preconditioner(C, "diag"), problems.start_block(n, b, seed=seed)
+
+
+@pytest.mark.parametrize("seed,p_mode", [(2, "thick"), (0, "lobpcg")])
+def test_locking_converges_to_dense(seed, p_mode):
+    # soft locking with adaptive m (remarks after Algorithm 2): once leading
+    # pairs are locked, W, S_l and P are built for the trailing columns only and
+    # the S recursion runs on the trailing blocks of M_A, M_B; the result must
+    # still be the k eigenvalues nearest sigma (LAPACK zggev)
+    n, k = 300, 4
+    As, Bs, sigma, T, V0 = _dd_pencil(n, seed, k)
+    r = O.gplhr(As, Bs, sigma, k, V0, T, tol=1e-11, maxit=100, locking=True, p_mode=p_mode)
+    assert r.converged
+    ref = nearest(sla.eigvals(As.toarray(), Bs.toarray()), sigma, k)
+    assert match_err(r.lam[:k], ref) < 1e-9
+    qs = [q for q, _ in r.lock_history]
+    assert qs == sorted(qs) and max(qs) == k - 1
+    # m = floor(m0 b / (b - q)): q = 3 of b = 4 gives m = 4
+    assert all(mm == min(4 // (4 - q), 20) for q, mm in r.lock_history)
+    assert (3, 4) in r.lock_history
+
+
+def test_locking_without_converged_pairs_is_the_plain_iteration():
+    n, k = 300, 4
+    As, Bs, sigma, T, V0 = _dd_pencil(n, 2, k)
+    r1 = O.gplhr(As, Bs, sigma, k, V0, T, tol=0.0, maxit=6, locking=True)
+    r0 = O.gplhr(As, Bs, sigma, k, V0, T, tol=0.0, maxit=6)
+    assert all(q == 0 for q, _ in r1.lock_history)
+    for a, b in zip(r1.lam_history, r0.lam_history):
+        assert np.array_equal(a, b)
 
 
 def test_random_pencil_family_matches_zggev():
