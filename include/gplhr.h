@@ -72,13 +72,21 @@ typedef struct {
 enum {
     GPLHR_PRECOND_NONE = 0,   /* T = I                                          */
     GPLHR_PRECOND_DIAG = 1,   /* T = diag(C)^{-1}                               */
-    GPLHR_PRECOND_JACOBI = 2  /* `sweeps` damped Jacobi steps on C w = r from
+    GPLHR_PRECOND_JACOBI = 2, /* `sweeps` damped Jacobi steps on C w = r from
                                  w_0 = 0: w_{t+1} = w_t + omega diag(C)^{-1}(r - C w_t) */
+    GPLHR_PRECOND_GMRES = 3   /* the stronger T of Section 4: `steps` block GMRES
+                                 steps on C W = R (all columns of the block at
+                                 once) from W_0 = 0, right-preconditioned by
+                                 `inner` (NONE, DIAG or JACOBI with sweeps,
+                                 omega): W = M X with X in the block Krylov space
+                                 of (C M, R) minimising ||R - C M X||_F          */
 };
 typedef struct {
     int kind;
-    int sweeps;    /* JACOBI only, >= 1 */
-    double omega;  /* JACOBI only, damping factor in (0, 2) */
+    int sweeps;    /* JACOBI (also as the GMRES inner step): >= 1 */
+    double omega;  /* JACOBI (also as the GMRES inner step): damping in (0, 2) */
+    int steps;     /* GMRES only: block steps s >= 1 with s * block <= 64 */
+    int inner;     /* GMRES only: the right preconditioner M (a kind < GMRES) */
 } gplhr_precond;
 
 enum { GPLHR_FP64 = 0, GPLHR_MIXED = 1 };
@@ -86,6 +94,10 @@ enum { GPLHR_FP64 = 0, GPLHR_MIXED = 1 };
  * (eq. P1, the paper's default), the previous V (with the projections of step 22
  * this spans the same space as the LOBPCG-style eq. P_lobpcg), or none. */
 enum { GPLHR_P_THICK = 0, GPLHR_P_LOBPCG = 1, GPLHR_P_NONE = 2 };
+/* Iterated form: Schur vectors (Algorithm 2, the default) or approximate
+ * eigenvectors with Rayleigh-quotient eigenvalues (GPLHR-EIG, Algorithm 3 of
+ * Appendix A). */
+enum { GPLHR_ALG_SCHUR = 0, GPLHR_ALG_EIG = 1 };
 
 typedef struct {
     int precision;      /* GPLHR_FP64: every block in complex128.
@@ -123,11 +135,19 @@ typedef struct {
                            so that the trial subspace keeps its size; 0 (default)
                            disables it                                           */
     int m_max;          /* upper bound of the adaptive m under locking (>= 1)    */
+    int algorithm;      /* GPLHR_ALG_SCHUR (default) or GPLHR_ALG_EIG.  EIG keeps
+                           X = V R_x (V orthonormal, unit-norm columns of X),
+                           Lambda_A = diag(X^H A X), Lambda_B = diag(X^H B X),
+                           builds W and S_l from A X Lambda_B - B X Lambda_A,
+                           and takes X and P from the eigenvectors of the
+                           projected pencil nearest sigma.  Not combined with
+                           locking; in MIXED precision P restarts empty when the
+                           FP64 phase begins                                     */
 } gplhr_options;
 
 /* Fill *opt with defaults: FP64, tol 1e-10, max_iter 500, arnoldi_m 1, thick P,
  * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0,
- * proj_before_T 1, locking 0, m_max 20. */
+ * proj_before_T 1, locking 0, m_max 20, algorithm SCHUR. */
 void gplhr_default_options(gplhr_options *opt);
 
 /* Set up the operator C = A - sigma B on the union sparsity pattern, its
@@ -165,7 +185,8 @@ gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B,
 gplhr_status gplhr_iterate(gplhr_t h, int max_iter, int *n_converged,
                            double *max_rel_resid);
 
-/* Copy out the partial generalized Schur form (Algorithm 2 output).
+/* Copy out the partial generalized Schur form (Algorithm 2 output).  STATE for
+ * a handle created with GPLHR_ALG_EIG, which keeps no Schur factors.
  * V, Q    device n-by-k complex128, row-major, ld = k (either may be NULL).
  * RA, RB  host k-by-k complex128 column-major (either may be NULL).  For the
  *         standard problem RA receives R = M_B^{-1} M_A and RB the identity.
@@ -179,6 +200,16 @@ gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB
 /* Copy the unit-norm Rayleigh-Ritz eigenvectors x_j = V z_j (device n-by-k
  * complex128 row-major, ld = k), in the order of gplhr_get_schur's lambda. */
 gplhr_status gplhr_get_eigvecs(gplhr_t h, void *X);
+
+/* Copy out the partial eigendecomposition A X Lambda_B = B X Lambda_A that
+ * GPLHR-EIG (Algorithm 3) iterates; STATE for an Algorithm 2 handle.
+ * X        device n-by-k complex128 row-major, ld = k, unit-norm columns
+ *          (may be NULL).
+ * LA, LB   host k complex128 each: diag(X^H A X), diag(X^H B X); the
+ *          eigenvalue approximations are LA[j] / LB[j] (either may be NULL).
+ * rel_resid host k doubles: ||A x_j - lambda_j B x_j|| / ||A x_j|| (may be NULL).
+ * Synchronises the handle's stream. */
+gplhr_status gplhr_get_eig(gplhr_t h, void *X, double *LA, double *LB, double *rel_resid);
 
 /* Gradient of a real loss L(lambda_1..lambda_k) with respect to the stored
  * values of A and B.  grad_lambda (host, k complex128) holds

@@ -136,7 +136,47 @@ def q_free_factors(RA: np.ndarray, RB: np.ndarray):
 # preconditioners T ~ (A - sigma B)^{-1}  (Section 4)
 # --------------------------------------------------------------------------
 
-def make_preconditioner(C: sp.csr_matrix, kind: str, sweeps: int = 3, omega: float = 0.7
+def block_gmres(C: sp.csr_matrix, R: np.ndarray, M: Callable[[np.ndarray], np.ndarray],
+                steps: int) -> np.ndarray:
+    """``steps`` block GMRES steps on C W = R from W_0 = 0 with the right
+    preconditioner M (the inner solve that Section 4 suggests as a stronger T;
+    block form as recommended there).
+
+    Definition: with K = span{R, (C M) R, ..., (C M)^{s-1} R} (block Krylov
+    space), W = M X where X in K minimises ||R - C M X||_F.  Computed by block
+    Arnoldi (block modified Gram-Schmidt, Householder QR of each new block) and
+    the small least-squares problem min_Y ||E_1 beta - Hbar Y||_F.
+    """
+    a = R.shape[1]
+    s = steps
+    V0, beta = _qr_pos(R)
+    basis = [V0]
+    H = np.zeros(((s + 1) * a, s * a), dtype=complex)
+    for j in range(s):
+        Wn = C @ M(basis[j])
+        for i in range(j + 1):
+            Hij = basis[i].conj().T @ Wn
+            Wn = Wn - basis[i] @ Hij
+            H[i * a:(i + 1) * a, j * a:(j + 1) * a] = Hij
+        Vn, Hn = _qr_pos(Wn)
+        H[(j + 1) * a:(j + 2) * a, j * a:(j + 1) * a] = Hn
+        basis.append(Vn)
+    E = np.zeros(((s + 1) * a, a), dtype=complex)
+    E[:a] = beta
+    Y = np.linalg.lstsq(H, E, rcond=None)[0]
+    return M(np.hstack(basis[:s]) @ Y)
+
+
+def _qr_pos(X: np.ndarray):
+    """X = Q R, Householder QR with R's diagonal made real non-negative (the Q
+    of ``orth`` together with its triangular factor)."""
+    Qx, Rx = sla.qr(X, mode="economic")
+    ph = _unit_phase(np.diag(Rx))
+    return Qx * ph[None, :], Rx * ph.conj()[:, None]
+
+
+def make_preconditioner(C: sp.csr_matrix, kind: str, sweeps: int = 3, omega: float = 0.7,
+                        steps: int = 2, inner: str = "jacobi"
                         ) -> Callable[[np.ndarray], np.ndarray]:
     """T applied to a block.
 
@@ -144,6 +184,9 @@ def make_preconditioner(C: sp.csr_matrix, kind: str, sweeps: int = 3, omega: flo
     kind = "diag":     T = diag(C)^{-1}.
     kind = "jacobi":   ``sweeps`` damped Jacobi steps on C w = r from w_0 = 0:
                        w_{t+1} = w_t + omega diag(C)^{-1} (r - C w_t).
+    kind = "gmres":    ``steps`` block GMRES steps on C w = r (``block_gmres``)
+                       right-preconditioned by the ``inner`` kind
+                       ("identity", "diag" or "jacobi" with sweeps, omega).
     kind = "exact":    T = C^{-1} by sparse LU.
     """
     if kind == "identity":
@@ -158,6 +201,9 @@ def make_preconditioner(C: sp.csr_matrix, kind: str, sweeps: int = 3, omega: flo
                 Wb = Wb + omega * (R - C @ Wb) / d[:, None]
             return Wb
         return apply
+    if kind == "gmres":
+        M = make_preconditioner(C, inner, sweeps, omega)
+        return lambda R: block_gmres(C, R, M, steps)
     if kind == "exact":
         lu = spla.splu(sp.csc_matrix(C))
         return lambda R: lu.solve(np.ascontiguousarray(R))
@@ -359,6 +405,126 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
                        lock_history=lock_history, trace=trace)
 
 
+@dataclass
+class GplhrEigResult:
+    X: np.ndarray            # unit-norm approximate eigenvectors (n x b)
+    alpha: np.ndarray        # diag(X^* A X)  (Lambda_A)
+    beta: np.ndarray         # diag(X^* B X)  (Lambda_B)
+    lam: np.ndarray          # alpha / beta, in the column order of X
+    rho: np.ndarray          # ||A x - lam B x|| / ||A x||
+    iterations: int
+    converged: bool
+    history: list = field(default_factory=list)
+    lam_history: list = field(default_factory=list)
+
+
+def _unit_columns_and_forms(A, Bm, X):
+    X = X / np.linalg.norm(X, axis=0)[None, :]
+    AX = A @ X
+    BX = Bm @ X
+    alpha = np.einsum("ij,ij->j", X.conj(), AX)
+    beta = np.einsum("ij,ij->j", X.conj(), BX)
+    return X, AX, BX, alpha, beta
+
+
+def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
+              m: int = 1, tol: float = 1e-10, maxit: int = 500, p_mode: str = "thick",
+              callback: Optional[Callable] = None) -> GplhrEigResult:
+    """Algorithm 3 (GPLHR-EIG, Appendix A): the eigenvector form.
+
+    The iterate is a block X of unit-norm approximate eigenvectors with the
+    diagonal bilinear forms Lambda_A = diag(X^* A X), Lambda_B = diag(X^* B X);
+    the eigenvalue approximations are their ratios (Rayleigh quotients).  The
+    residual block is A X Lambda_B - B X Lambda_A, the S recursion applies the
+    same diagonal forms, and the projected pencil (U^* A Z, U^* B Z) is solved
+    by a full eigendecomposition ordered by closeness to sigma.  b = X0.shape[1]
+    columns are iterated; the k leading ones decide convergence, measured by
+    ||A x_j - lambda_j B x_j|| / ||A x_j|| at the Rayleigh quotient lambda_j.
+
+    p_mode  "thick":  P = Z Ybar(:, b+1:2b) (step 26);
+            "lobpcg": P = W Y_W + S Y_S + P Y_P (step 25 kept, step 26 off);
+            "none":   no P block.
+    Reading: the test-basis step projects against Q before orthonormalising
+    (as for Algorithm 2).
+    """
+    A = sp.csr_matrix(A)
+    std = B is None
+    Bm = sp.identity(A.shape[0], format="csr", dtype=complex) if std else sp.csr_matrix(B)
+    C = (A - sigma * Bm).tocsr()
+    b = X0.shape[1]
+    # steps 1-2
+    X, AX, BX, alpha, beta = _unit_columns_and_forms(A, Bm, X0.astype(complex))
+    Q = C @ X
+    P = None
+    history, lam_history = [], []
+    it = 0
+    while True:
+        lam = alpha / beta
+        rho = np.linalg.norm(AX - BX * lam[None, :], axis=0) / np.linalg.norm(AX, axis=0)
+        history.append(float(np.max(rho[:k])))
+        lam_history.append(lam[:k].copy())
+        if callback is not None:
+            callback(it, lam, rho)
+        if np.max(rho[:k]) <= tol or it >= maxit:
+            break
+        it += 1
+        # step 4
+        V = orth(X)
+        Q = orth(Q)
+        L = V if std else Q
+
+        def proj_V(Y):
+            return Y - V @ (V.conj().T @ Y)
+
+        def proj_left(Y):
+            return Y - L @ (L.conj().T @ Y)
+
+        # steps 5-9: W = (I - VV^*) T (I - QQ^*) (A X Lambda_B - B X Lambda_A)
+        W = orth(proj_V(precond(proj_left(AX * beta[None, :] - BX * alpha[None, :]))))
+        # steps 10-17
+        S_prev = W
+        S = np.zeros((A.shape[0], 0), dtype=complex)
+        for _ in range(m):
+            Sl = proj_V(precond(proj_left((A @ S_prev) * beta[None, :]
+                                          - (Bm @ S_prev) * alpha[None, :])))
+            Sl = Sl - W @ (W.conj().T @ Sl)
+            Sl = Sl - S @ (S.conj().T @ Sl)
+            Sl = orth(Sl)
+            S = np.hstack([S, Sl])
+            S_prev = Sl
+        # step 18
+        if P is not None:
+            P = P - V @ (V.conj().T @ P)
+            P = P - W @ (W.conj().T @ P)
+            P = P - S @ (S.conj().T @ P)
+            P = orth(P)
+        # steps 19-21
+        Z = np.hstack([V, W, S] + ([P] if P is not None else []))
+        Qh = C @ Z[:, b:]
+        Qh = Qh - Q @ (Q.conj().T @ Qh)
+        U = np.hstack([Q, orth(Qh)])
+        # steps 22-23: eigenvectors of (U^* A Z, U^* B Z), nearest sigma first
+        ev, Yb = sla.eig(U.conj().T @ (A @ Z), U.conj().T @ (Bm @ Z), homogeneous_eigvals=True)
+        d = np.array([_dist(ev[0][j], ev[1][j], sigma) for j in range(ev.shape[1])])
+        Yb = Yb[:, np.argsort(d, kind="stable")]
+        Y = Yb[:, :b]
+        # steps 24-26
+        Pn = Z[:, b:] @ Y[b:, :]
+        X = V @ Y[:b, :] + Pn
+        Q = C @ X
+        if p_mode == "thick":
+            P = Z @ Yb[:, b:2 * b] if Z.shape[1] >= 2 * b else None
+        elif p_mode == "lobpcg":
+            P = Pn
+        else:
+            P = None
+        # step 27
+        X, AX, BX, alpha, beta = _unit_columns_and_forms(A, Bm, X)
+    return GplhrEigResult(X=X, alpha=alpha, beta=beta, lam=lam, rho=rho, iterations=it,
+                          converged=bool(np.max(rho[:k]) <= tol), history=history,
+                          lam_history=lam_history)
+
+
 def solve_problem(problem, tol: Optional[float] = None, maxit: int = 500, **kw) -> GplhrResult:
     """Run the oracle on a ``problems.Problem`` (inputs only; no method code
     lives there)."""
@@ -366,6 +532,8 @@ def solve_problem(problem, tol: Optional[float] = None, maxit: int = 500, **kw) 
     B = None if problem.B is None else problem.B.to_scipy()
     Bm = sp.identity(A.shape[0], format="csr") if B is None else B
     C = (A - problem.sigma * Bm).tocsr()
-    T = make_preconditioner(C, problem.precond, problem.sweeps, problem.omega)
-    return gplhr(A, B, problem.sigma, problem.k, problem.V0, T,
-                 tol=problem.tol if tol is None else tol, maxit=maxit, **kw)
+    T = make_preconditioner(C, problem.precond, problem.sweeps, problem.omega,
+                            problem.steps, problem.inner)
+    solver = gplhr_eig if kw.pop("algorithm", "schur") == "eig" else gplhr
+    return solver(A, B, problem.sigma, problem.k, problem.V0, T,
+                  tol=problem.tol if tol is None else tol, maxit=maxit, **kw)

@@ -56,6 +56,7 @@ void gplhr_default_options(gplhr_options *opt) {
     opt->proj_before_T = 1;
     opt->locking = 0;
     opt->m_max = 20;
+    opt->algorithm = GPLHR_ALG_SCHUR;
 }
 
 gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B, double sigma_re,
@@ -101,6 +102,7 @@ gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB
     if (!h) return GPLHR_ERR_ARG;
     return guard(h, [&]() {
         gplhr::Ctx &c = h->c;
+        if (c.eig) throw gplhr::Error(-8, "the eigenvector form keeps no Schur factors (gplhr_get_eig)");
         if ((int)c.lam_h.size() < c.k || (int)c.rho_h.size() < c.k || c.MB.r < c.k)
             throw gplhr::Error(-8, "no iterate available");
         c.copy_out(V, Q);
@@ -139,6 +141,22 @@ gplhr_status gplhr_get_eigvecs(gplhr_t h, void *X) {
     return guard(h, [&]() {
         h->c.eigvecs(static_cast<double2 *>(X));
         return 0;
+    });
+}
+
+gplhr_status gplhr_get_eig(gplhr_t h, void *X, double *LA, double *LB, double *rel_resid) {
+    if (!h) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        gplhr::Ctx &c = h->c;
+        if (!c.eig) throw gplhr::Error(-8, "gplhr_get_eig needs a GPLHR_ALG_EIG handle");
+        if ((int)c.alpha_h.size() < c.k || (int)c.rho_h.size() < c.k)
+            throw gplhr::Error(-8, "no iterate available");
+        if (X) c.eigvecs(static_cast<double2 *>(X));
+        const int k = c.k;
+        if (LA) std::memcpy(LA, c.alpha_h.data(), sizeof(gplhr::cd) * k);
+        if (LB) std::memcpy(LB, c.beta_h.data(), sizeof(gplhr::cd) * k);
+        if (rel_resid) std::memcpy(rel_resid, c.rho_h.data(), sizeof(double) * k);
+        return c.converged ? 0 : 1;
     });
 }
 

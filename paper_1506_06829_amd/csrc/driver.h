@@ -25,6 +25,8 @@ struct Work {
     const T *dw = nullptr;     // omega / diag(C)
     T *Z = nullptr, *CZ = nullptr, *BZ = nullptr, *U = nullptr;   // n x smax
     T *R = nullptr, *J1 = nullptr, *J2 = nullptr;                  // n x b
+    T *G = nullptr;                    // block GMRES basis, n x (steps+1) b
+    T *Gz = nullptr, *Gx = nullptr;    // block GMRES temporaries, n x b
 };
 
 struct Timer {
@@ -41,6 +43,7 @@ struct Ctx {
     static constexpr int RESID_BLOCKS = 1024;
     static constexpr int EYE_N = 64;
     static constexpr int REFRESH_EVERY = 20;
+    static constexpr size_t GM_SLOT = 64 * 16;   // entries per block GMRES small factor
 
     std::string err;
     hipStream_t st = nullptr;
@@ -54,6 +57,7 @@ struct Ctx {
     cd sigma;
     BKind bk = B_IDENT;
     bool mixed = false, xcd_remap = false;
+    bool eig = false;   // GPLHR-EIG (Algorithm 3) instead of the Schur form
     int phase = 1;
     bool converged = false, checked = false;
 
@@ -78,15 +82,21 @@ struct Ctx {
     // small device buffers (FP64 complex)
     double2 *part = nullptr, *g0 = nullptr, *g1 = nullptr, *rinv = nullptr, *eye = nullptr;
     double2 *coefY = nullptr, *coefL = nullptr, *M1 = nullptr, *M2 = nullptr;
+    // coefficients of the S recursion: M_B, sigma M_B - M_A (Algorithm 2, the
+    // same buffers as M1, M2) or Lambda_B, sigma Lambda_B - Lambda_A (Algorithm 3)
+    double2 *M1s = nullptr, *M2s = nullptr;
     double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
     double2 *xvec = nullptr;
     double2 *ucoef = nullptr;   // combined update coefficients
+    double2 *gmH = nullptr, *gmY = nullptr;   // block GMRES small factors (device)
+    double2 *hgm = nullptr;                   // their pinned host staging
     int *dstatus = nullptr;
     double2 *hpin = nullptr;   // pinned host staging
 
     // host state of the iteration
     small::Mat MA, MB, RA, RB, Zr_h;
-    std::vector<cd> lam_h;
+    small::Mat Rx;                       // Algorithm 3: X = V Rx (unit columns)
+    std::vector<cd> lam_h, alpha_h, beta_h;
     std::vector<double> rho_h, resid_h, history;
     double max_rho = INFINITY;
     int nconv = 0, nlead = 0;   // leading pairs meeting tol: of the k wanted, of all b
@@ -126,9 +136,14 @@ struct Ctx {
     template <typename T>
     void spmm_b(const T *X, int ldx, T *Y, int ldy, int w);
     template <typename T> void apply_T(T *dest, int ldd, int dcol, int w);
+    template <typename T>
+    void apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int w);
+    template <typename T> void apply_gmres(T *dest, int ldd, int dcol, int w);
     template <typename T> void srr_and_update(int s_cur, int p_cols);
     void update_locking();
     template <typename T> void init_from_Z(int w0);
+    template <typename T> void init_eig();
+    template <typename T> void eig_orthonormalise();
     template <typename T> void iterate_once();
     template <typename T> void refresh_products();
     template <typename T> void check();

@@ -56,12 +56,13 @@ Ctx::~Ctx() {
     dfree(a_rp); dfree(a_ci); dfree(a_val);
     dfree(b_rp); dfree(b_ci); dfree(b_val); dfree(b_val32);
     dfree(bd); dfree(bd32); dfree(dinv); dfree(dinv32); dfree(dw); dfree(dw32);
-    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); }
-    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); }
+    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); }
+    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); }
     dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(eye); dfree(coefY); dfree(coefL);
-    dfree(M1); dfree(M2); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
-    dfree(dstatus); dfree(xvec); dfree(ucoef);
+    dfree(M1); dfree(M2); dfree(M1s); dfree(M2s); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
+    dfree(dstatus); dfree(xvec); dfree(ucoef); dfree(gmH); dfree(gmY);
     if (hpin) (void)hipHostFree(hpin);
+    if (hgm) (void)hipHostFree(hgm);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,30 +185,117 @@ void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy, int wc) {
     spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * wc * sizeof(T);
 }
 
-// dest(:, dcol:dcol+wc) = T R  (R = Work.R, ld b, wc <= b columns)
+// dest = M in for a basic preconditioner kind (NONE, DIAG, JACOBI); wc columns.
 template <typename T>
-void Ctx::apply_T(T *dest, int ldd, int dcol, int wc) {
+void Ctx::apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int wc) {
     Work<T> &w = W<T>();
-    ++n_prec;
-    if (pre.kind == GPLHR_PRECOND_NONE) {
-        launch_scale_rows<T>(st, n, wc, w.R, b, nullptr, dest + dcol, ldd);
-    } else if (pre.kind == GPLHR_PRECOND_DIAG) {
-        launch_scale_rows<T>(st, n, wc, w.R, b, w.dinv, dest + dcol, ldd);
+    if (kind == GPLHR_PRECOND_NONE) {
+        launch_scale_rows<T>(st, n, wc, in, ldi, nullptr, dest, ldd);
+    } else if (kind == GPLHR_PRECOND_DIAG) {
+        launch_scale_rows<T>(st, n, wc, in, ldi, w.dinv, dest, ldd);
     } else {
         // w_1 = omega D^{-1} r; w_{t+1} = w_t + omega D^{-1} (r - C w_t)
         if (pre.sweeps == 1) {
-            launch_scale_rows<T>(st, n, wc, w.R, b, w.dw, dest + dcol, ldd);
+            launch_scale_rows<T>(st, n, wc, in, ldi, w.dw, dest, ldd);
             return;
         }
-        launch_scale_rows<T>(st, n, wc, w.R, b, w.dw, w.J1, b);
+        launch_scale_rows<T>(st, n, wc, in, ldi, w.dw, w.J1, b);
         T *cur = w.J1;
         for (int t = 1; t < pre.sweeps; ++t) {
             const bool last = (t == pre.sweeps - 1);
-            T *o = last ? dest + dcol : (cur == w.J1 ? w.J2 : w.J1);
-            spmm_c<T>(cur, b, o, last ? ldd : b, wc, 1, w.R, b);
+            T *o = last ? dest : (cur == w.J1 ? w.J2 : w.J1);
+            spmm_c<T>(cur, b, o, last ? ldd : b, wc, 1, in, ldi);
             cur = o;
         }
     }
+}
+
+// dest(:, dcol:dcol+wc) = T R  (R = Work.R, ld b, wc <= b columns)
+template <typename T>
+void Ctx::apply_T(T *dest, int ldd, int dcol, int wc) {
+    ++n_prec;
+    if (pre.kind == GPLHR_PRECOND_GMRES)
+        apply_gmres<T>(dest, ldd, dcol, wc);
+    else
+        apply_inner<T>(pre.kind, W<T>().R, b, dest + dcol, ldd, wc);
+}
+
+// Block GMRES(s) on C X = R from X_0 = 0 with the right preconditioner M:
+// block Arnoldi on C M from V_0 beta = R (classical block Gram-Schmidt, two
+// passes; Cholesky-QR, two passes), then min ||E_1 beta - Hbar Y||_F on the
+// host and dest = M (V_{0..s-1} Y).  One host synchronisation per call.
+template <typename T>
+void Ctx::apply_gmres(T *dest, int ldd, int dcol, int a) {
+    Work<T> &w = W<T>();
+    const int s = pre.steps, lg = (s + 1) * b;
+    T *G = w.G;
+    // small factors: slot(j, 0/1) = Gram-Schmidt coefficients of both passes
+    // for step j, slot(j, 2/3) = Cholesky factors of both passes (j = s: beta)
+    auto slot = [&](int j, int kind) { return gmH + (size_t)(j * 4 + kind) * GM_SLOT; };
+    auto qr2 = [&](int col, int j) {
+        for (int p = 0; p < 2; ++p) {
+            gram<T>(G + col, lg, a, G + col, lg, a, nullptr, g0);
+            launch_chol_rinv(st, a, g0, rinv, dstatus, slot(j, 2 + p));
+            UpdTerm<T> t;
+            t.in = G; t.ld = lg; t.col = col; t.w = a; t.M = rinv; t.ldm = a;
+            update<T>(G, lg, a, col, a, 0, false, 1, &t);
+        }
+    };
+    launch_scale_rows<T>(st, n, a, w.R, b, nullptr, G, lg);
+    qr2(0, s);
+    for (int j = 0; j < s; ++j) {
+        apply_inner<T>(pre.inner, G + j * a, lg, w.Gz, b, a);          // M V_j
+        spmm_c<T>(w.Gz, b, G + (j + 1) * a, lg, a, 0, nullptr, 0);     // C M V_j
+        const int wv = (j + 1) * a;
+        for (int p = 0; p < 2; ++p) {
+            gram<T>(G, lg, wv, G + wv, lg, a, nullptr, slot(j, p));
+            UpdTerm<T> t;
+            t.in = G; t.ld = lg; t.col = 0; t.w = wv; t.M = slot(j, p); t.ldm = wv;
+            t.alpha = make_double2(-1.0, 0.0);
+            update<T>(G, lg, a, wv, a, 0, true, 1, &t);
+        }
+        qr2(wv, j);
+    }
+    const size_t tot = (size_t)(s + 1) * 4 * GM_SLOT;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hgm, gmH, tot * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    tflush();
+    const cd *h = reinterpret_cast<const cd *>(hgm);
+    auto sl = [&](int j, int kind) { return h + (size_t)(j * 4 + kind) * GM_SLOT; };
+    auto tri = [&](int j) {   // R2 R1 of the two Cholesky-QR passes
+        Mat r1(a, a), r2(a, a);
+        std::memcpy(r1.data(), sl(j, 2), (size_t)a * a * sizeof(cd));
+        std::memcpy(r2.data(), sl(j, 3), (size_t)a * a * sizeof(cd));
+        return small::matmul(r2, r1);
+    };
+    Mat Hb((s + 1) * a, s * a), E((s + 1) * a, a);
+    const Mat beta = tri(s);
+    for (int jj = 0; jj < a; ++jj)
+        for (int ii = 0; ii < a; ++ii) E(ii, jj) = beta(ii, jj);
+    for (int j = 0; j < s; ++j) {
+        const int wv = (j + 1) * a;
+        const cd *h1 = sl(j, 0), *h2 = sl(j, 1);
+        for (int jj = 0; jj < a; ++jj)
+            for (int ii = 0; ii < wv; ++ii)
+                Hb(ii, j * a + jj) = h1[ii + (size_t)jj * wv] + h2[ii + (size_t)jj * wv];
+        const Mat r = tri(j);
+        for (int jj = 0; jj < a; ++jj)
+            for (int ii = 0; ii < a; ++ii) Hb(wv + ii, j * a + jj) = r(ii, jj);
+    }
+    for (const cd &v : Hb.a)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+            throw Error(-6, "non-finite block GMRES Hessenberg matrix");
+    Mat Qh, Rh;
+    small::qr_thin(Hb, Qh, Rh);
+    const Mat Y = small::tri_solve_upper(Rh, small::matmul_hn(Qh, E));
+    std::memcpy(hgm, Y.data(), (size_t)s * a * a * sizeof(cd));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(gmY, hgm, (size_t)s * a * a * sizeof(double2), hipMemcpyHostToDevice, st));
+    UpdTerm<T> t;
+    t.in = G; t.ld = lg; t.col = 0; t.w = s * a; t.M = gmY; t.ldm = s * a;
+    update<T>(w.Gx, b, a, 0, a, 0, false, 1, &t);
+    apply_inner<T>(pre.inner, w.Gx, b, dest + dcol, ldd, a);
+    // hgm is written again only after the next call's synchronisation, which
+    // follows this upload on the stream.
 }
 
 // ---------------------------------------------------------------------------
@@ -245,6 +333,41 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     const bool lobpcg = (opt.p_mode == GPLHR_P_LOBPCG);
     const bool thick = (opt.p_mode == GPLHR_P_THICK);
     const int nkeep = std::min(thick ? b + p_cols : b, s_cur);
+    const int offP = smax - b;
+    if (eig) {
+        // Algorithm 3, steps 22-26: eigenvectors Ybar of the projected pencil
+        // nearest sigma; X = Z Ybar(:, 1:b), P = Z Ybar(:, b+1:b+p) (thick) or
+        // P = [W S P] Ybar(b+1:s, 1:b) (LOBPCG-style, step 25)
+        Mat Yb;
+        if (!small::harmonic_eig(K, Gm, nkeep, Yb))
+            throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
+                            "(Proposition 3.1)");
+        small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        int nc = Yb.c;
+        cd *hc = reinterpret_cast<cd *>(hpin);
+        std::memcpy(hc, Yb.data(), (size_t)s_cur * nc * sizeof(cd));
+        if (lobpcg && p_cols > 0 && s_cur > b) {
+            cd *ext = hc + (size_t)s_cur * nc;
+            for (int j = 0; j < p_cols; ++j)
+                for (int i = 0; i < s_cur; ++i)
+                    ext[(size_t)j * s_cur + i] = (i < b) ? cd(0.0, 0.0) : Yb(i, (b - p_cols) + j);
+            nc += p_cols;
+        }
+        GPLHR_HIP_CHECK(hipMemcpyAsync(coefY, hpin, (size_t)s_cur * nc * sizeof(double2), hipMemcpyHostToDevice, st));
+        UpdTerm<T> t;
+        t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
+        t.in = w.Z;
+        update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
+        t.in = w.CZ;
+        update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
+        if (bk == B_SPARSE) {
+            t.in = w.BZ;
+            update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
+        }
+        pw = nc - b;
+        eig_orthonormalise<T>();
+        return;
+    }
     small::SrrResult r;
     if (!small::harmonic_srr(K, Gm, sigma, b, nkeep, r))
         throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
@@ -280,7 +403,6 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     GPLHR_HIP_CHECK(hipMemcpyAsync(M2, hpin + (size_t)s_cur * (nc + b) + (size_t)b * b, (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
     // a10: V = Z Y_R, P = Z Y_P (and the same for CZ, BZ); Q = U Y_L.  P lands
     // at its between-iterations slot smax - b.
-    const int offP = smax - b;
     UpdTerm<T> t;
     t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
     t.in = w.Z;
@@ -315,6 +437,53 @@ void Ctx::init_from_Z(int w0) {
     srr_and_update<T>(w0, (w0 > b && opt.p_mode != GPLHR_P_NONE) ? b - q : 0);
 }
 
+// Algorithm 3 bookkeeping on the device: the new X in Z(:, 0:b) becomes
+// X = V Rx with V orthonormal (two Cholesky-QR passes, mirrored onto C X and
+// B X) and Rx scaled to unit-norm columns of X (step 27); Q = orth(C V), whose
+// span is that of C X (step 4).
+template <typename T>
+void Ctx::eig_orthonormalise() {
+    Work<T> &w = W<T>();
+    const int ld = smax;
+    T *bz = (bk == B_SPARSE) ? w.BZ : nullptr;
+    const size_t bb = (size_t)b * b;
+    for (int p = 0; p < 2; ++p) {
+        gram<T>(w.Z, ld, b, w.Z, ld, b, nullptr, g0);
+        launch_chol_rinv(st, b, g0, rinv, dstatus, g1 + p * bb);
+        UpdTerm<T> t;
+        t.ld = ld; t.col = 0; t.w = b; t.M = rinv; t.ldm = b;
+        t.in = w.Z;  update<T>(w.Z, ld, b, 0, b, 0, false, 1, &t);
+        t.in = w.CZ; update<T>(w.CZ, ld, b, 0, b, 0, false, 1, &t);
+        if (bz) { t.in = bz; update<T>(bz, ld, b, 0, b, 0, false, 1, &t); }
+    }
+    launch_scale_rows<T>(st, n, b, w.CZ, ld, nullptr, w.U, ld);
+    cholqr<T>(w.U, ld, 0, b, 2, nullptr, nullptr);
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, g1, 2 * bb * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    Mat r1(b, b), r2(b, b);
+    std::memcpy(r1.data(), hpin, bb * sizeof(cd));
+    std::memcpy(r2.data(), hpin + bb, bb * sizeof(cd));
+    Rx = small::matmul(r2, r1);
+    for (int j = 0; j < b; ++j) {
+        double nrm = 0.0;
+        for (int i = 0; i <= j; ++i) nrm += std::norm(Rx(i, j));
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) throw Error(-6, "vanishing or non-finite eigenvector approximation");
+        for (int i = 0; i <= j; ++i) Rx(i, j) /= nrm;
+    }
+}
+
+// Steps 1-2 of Algorithm 3 from X = Z(:, 0:b) (X0, or the current X when the
+// FP64 phase begins): C X (and B X), X = V Rx, Q = orth(C V); P empty.
+template <typename T>
+void Ctx::init_eig() {
+    Work<T> &w = W<T>();
+    spmm_c<T>(w.Z, smax, w.CZ, smax, b, 0, nullptr, 0);
+    if (bk == B_SPARSE) spmm_b<T>(w.Z, smax, w.BZ, smax, b);
+    eig_orthonormalise<T>();
+    pw = 0;
+}
+
 // One GPLHR iteration (Algorithm 2, steps 6-31), with soft locking of the q
 // leading columns when enabled.
 template <typename T>
@@ -334,14 +503,16 @@ void Ctx::iterate_once() {
 
     // src block (width ws) -> new block of width a at dst:
     //   R = (A - sigma B) X M_B(., q:) + B X (sigma M_B - M_A)(., q:)   (moff selects
-    //   the columns q: of M for X = V and the trailing a-by-a block for X = S_l)
+    //   the columns q: of M for X = V and the trailing a-by-a block for X = S_l;
+    //   Algorithm 3 passes M_B = Rx Lambda_B, M_A = Rx Lambda_A for X = V and the
+    //   diagonal Lambda_B, Lambda_A for S_l)
     //   R <- (I - Q Q^H) R;  Y = T R;  Y <- (I - [V W S_<l] [.]^H) Y (two passes)
     //   Y <- orth(Y);  C Y (and B Y)
-    auto build = [&](int src, int ws, int moff, int dst) {
+    auto build = [&](int src, int ws, const double2 *m1, const double2 *m2, int moff, int dst) {
         UpdTerm<T> t[2];
-        t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = ws; t[0].M = M1 + moff; t[0].ldm = b;
+        t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = ws; t[0].M = m1 + moff; t[0].ldm = b;
         t[1].in = (bk == B_SPARSE) ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = ws;
-        t[1].M = M2 + moff; t[1].ldm = b; t[1].rowscale = bsc;
+        t[1].M = m2 + moff; t[1].ldm = b; t[1].rowscale = bsc;
         update<T>(w.R, b, a, 0, a, 0, false, 2, t);
         if (opt.proj_before_T) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
         apply_T<T>(Z, ld, dst, a);
@@ -350,9 +521,9 @@ void Ctx::iterate_once() {
         spmm_c<T>(Z + dst, ld, CZ + dst, ld, a, 0, nullptr, 0);
         if (bk == B_SPARSE) spmm_b<T>(Z + dst, ld, BZ + dst, ld, a);
     };
-    build(0, b, q * b, offW);                                        // W (steps 6-12)
+    build(0, b, M1, M2, q * b, offW);                                // W (steps 6-12)
     for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
-        build(offW + (l - 1) * a, a, q + q * b, offW + l * a);
+        build(offW + (l - 1) * a, a, eig ? M1s : M1, eig ? M2s : M2, q + q * b, offW + l * a);
 
     // step 22: P <- orth(P - [V W S][V W S]^H P), mirrored onto C P (and B P)
     if (pa > 0) {
@@ -434,7 +605,43 @@ void Ctx::check() {
     }
     std::vector<cd> lam;
     Mat Zr;
-    if (!small::ritz(Va, Vb, sigma, lam, Zr)) throw Error(-6, "Rayleigh-Ritz step failed");
+    if (eig) {
+        // Algorithm 3: x_j = V Rx(:, j); Lambda_A = diag(X^H A X), Lambda_B =
+        // diag(X^H B X); lambda_j = Lambda_A(j,j) / Lambda_B(j,j).  The next
+        // iteration's coefficients: Rx Lambda_B, Rx (sigma Lambda_B - Lambda_A)
+        // for the residual, Lambda_B, sigma Lambda_B - Lambda_A for S.
+        Zr = Rx;
+        const Mat ax = small::matmul(Va, Rx), bx = small::matmul(Vb, Rx);
+        alpha_h.assign(b, cd(0.0, 0.0));
+        beta_h.assign(b, cd(0.0, 0.0));
+        lam.assign(b, cd(0.0, 0.0));
+        for (int j = 0; j < b; ++j) {
+            for (int i = 0; i < b; ++i) {
+                alpha_h[j] += std::conj(Rx(i, j)) * ax(i, j);
+                beta_h[j] += std::conj(Rx(i, j)) * bx(i, j);
+            }
+            lam[j] = alpha_h[j] / beta_h[j];
+            if (!std::isfinite(lam[j].real()) || !std::isfinite(lam[j].imag()))
+                throw Error(-6, "Rayleigh quotient with x^H B x = 0");
+        }
+        cd *mh = reinterpret_cast<cd *>(hpin) + bb + 2 * b;
+        std::fill(mh, mh + 4 * bb, cd(0.0, 0.0));
+        for (int j = 0; j < b; ++j) {
+            const cd m2d = sigma * beta_h[j] - alpha_h[j];
+            for (int i = 0; i <= j; ++i) {
+                mh[i + (size_t)j * b] = Rx(i, j) * beta_h[j];
+                mh[bb + i + (size_t)j * b] = Rx(i, j) * m2d;
+            }
+            mh[2 * bb + j + (size_t)j * b] = beta_h[j];
+            mh[3 * bb + j + (size_t)j * b] = m2d;
+        }
+        GPLHR_HIP_CHECK(hipMemcpyAsync(M1, mh, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(M2, mh + bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(M1s, mh + 2 * bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(M2s, mh + 3 * bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+    } else {
+        if (!small::ritz(Va, Vb, sigma, lam, Zr)) throw Error(-6, "Rayleigh-Ritz step failed");
+    }
     lam_h = lam;
     Zr_h = Zr;
     std::memcpy(hpin, Zr.data(), bb * sizeof(cd));
@@ -476,7 +683,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
                 const gplhr_precond *T, const gplhr_options *o) {
     auto t0 = std::chrono::steady_clock::now();
     if (o) opt = *o; else gplhr_default_options(&opt);
-    if (T) pre = *T; else { pre.kind = GPLHR_PRECOND_NONE; pre.sweeps = 0; pre.omega = 0.0; }
+    if (T) pre = *T; else { pre = gplhr_precond{}; pre.kind = GPLHR_PRECOND_NONE; }
     st = static_cast<hipStream_t>(opt.hip_stream);
     sigma = sig;
     if (!A || !A->row_ptr || !A->col_idx || !A->val) throw Error(-1, "A must be a device CSR");
@@ -490,6 +697,10 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     if (k < 1 || b < k) throw Error(-1, "need 1 <= k <= block");
     if (m < 1) throw Error(-1, "arnoldi_m must be >= 1");
     if (opt.locking && opt.m_max < m) throw Error(-1, "m_max must be >= arnoldi_m");
+    if (opt.algorithm != GPLHR_ALG_SCHUR && opt.algorithm != GPLHR_ALG_EIG)
+        throw Error(-1, "unknown algorithm");
+    eig = (opt.algorithm == GPLHR_ALG_EIG);
+    if (eig && opt.locking) throw Error(-1, "locking is available for the Schur form only");
     if (opt.p_mode != GPLHR_P_THICK && opt.p_mode != GPLHR_P_LOBPCG && opt.p_mode != GPLHR_P_NONE)
         throw Error(-1, "unsupported p_mode");
     if (opt.precision != GPLHR_FP64 && opt.precision != GPLHR_MIXED) throw Error(-1, "bad precision");
@@ -498,9 +709,16 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         throw Error(-1, "(m+2)*block must be <= 48 and (m+3)*block <= 64");
     if (smax > n) throw Error(-1, "trial subspace (m+3)*block exceeds n");
     if (!(opt.tol >= 0.0)) throw Error(-1, "tol must be >= 0");
-    if (pre.kind == GPLHR_PRECOND_JACOBI && (pre.sweeps < 1 || !(pre.omega > 0.0 && pre.omega < 2.0)))
+    if (pre.kind < 0 || pre.kind > GPLHR_PRECOND_GMRES) throw Error(-1, "unknown preconditioner");
+    if (pre.kind == GPLHR_PRECOND_GMRES) {
+        if (pre.inner < 0 || pre.inner >= GPLHR_PRECOND_GMRES)
+            throw Error(-1, "GMRES inner preconditioner must be NONE, DIAG or JACOBI");
+        if (pre.steps < 1 || pre.steps * b > 64) throw Error(-1, "GMRES needs 1 <= steps and steps * block <= 64");
+    }
+    // the basic preconditioner applied (T itself, or M inside block GMRES)
+    const int ik = (pre.kind == GPLHR_PRECOND_GMRES) ? pre.inner : pre.kind;
+    if (ik == GPLHR_PRECOND_JACOBI && (pre.sweeps < 1 || !(pre.omega > 0.0 && pre.omega < 2.0)))
         throw Error(-1, "Jacobi needs sweeps >= 1 and 0 < omega < 2");
-    if (pre.kind < 0 || pre.kind > 2) throw Error(-1, "unknown preconditioner");
     if (!std::isfinite(sigma.real()) || !std::isfinite(sigma.imag())) throw Error(-1, "sigma must be finite");
 
     // A: validate and keep a copy (pattern + values) for the backward pass
@@ -546,7 +764,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     // a1: C = A - sigma B on the union pattern, its diagonal, the preconditioner
     c_nnz = build_shifted(st, n, a_rp, a_ci, a_val, bk == B_IDENT ? 0 : 1, b_rp, b_ci, b_val,
                           to_d2(sigma), &c_rp, &c_ci, &c_val);
-    if (pre.kind != GPLHR_PRECOND_NONE) {
+    if (ik != GPLHR_PRECOND_NONE) {
         double2 *dg = nullptr;
         dalloc(&dg, n);
         const int64_t zeros = extract_diag(st, n, c_rp, c_ci, c_val, dg);
@@ -556,7 +774,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         }
         dalloc(&dinv, n);
         launch_recip_scaled(st, n, dg, make_double2(1.0, 0.0), dinv);
-        if (pre.kind == GPLHR_PRECOND_JACOBI) {
+        if (ik == GPLHR_PRECOND_JACOBI) {
             dalloc(&dw, n);
             launch_recip_scaled(st, n, dg, make_double2(pre.omega, 0.0), dw);
         }
@@ -572,7 +790,11 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     dalloc(&wd.Z, blk_s); dalloc(&wd.CZ, blk_s); dalloc(&wd.U, blk_s);
     if (bk == B_SPARSE) dalloc(&wd.BZ, blk_s);
     dalloc(&wd.R, blk_b);
-    if (pre.kind == GPLHR_PRECOND_JACOBI && pre.sweeps > 1) { dalloc(&wd.J1, blk_b); dalloc(&wd.J2, blk_b); }
+    const bool jac2 = (ik == GPLHR_PRECOND_JACOBI && pre.sweeps > 1);
+    const bool gm = (pre.kind == GPLHR_PRECOND_GMRES);
+    const size_t blk_g = gm ? (size_t)n * (pre.steps + 1) * b : 0;
+    if (jac2) { dalloc(&wd.J1, blk_b); dalloc(&wd.J2, blk_b); }
+    if (gm) { dalloc(&wd.G, blk_g); dalloc(&wd.Gz, blk_b); dalloc(&wd.Gx, blk_b); }
     if (mixed) {
         dalloc(&c_val32, c_nnz);
         launch_c128_to_c64_flat(st, c_nnz, c_val, c_val32);
@@ -584,14 +806,21 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         dalloc(&wf.Z, blk_s); dalloc(&wf.CZ, blk_s); dalloc(&wf.U, blk_s);
         if (bk == B_SPARSE) dalloc(&wf.BZ, blk_s);
         dalloc(&wf.R, blk_b);
-        if (pre.kind == GPLHR_PRECOND_JACOBI && pre.sweeps > 1) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
+        if (jac2) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
+        if (gm) { dalloc(&wf.G, blk_g); dalloc(&wf.Gz, blk_b); dalloc(&wf.Gx, blk_b); }
     }
     dalloc(&part, PART_CAP);
     dalloc(&g0, 64 * 64); dalloc(&g1, 64 * 64); dalloc(&rinv, 64 * 64);
     dalloc(&eye, EYE_N * EYE_N); dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
-    dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
+    dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&M1s, 64 * 64); dalloc(&M2s, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
     dalloc(&dZr, 64 * 64); dalloc(&dlam, 64); dalloc(&rnorm, 64); dalloc(&dstatus, 1);
     dalloc(&ucoef, 128 * 64);
+    if (gm) {
+        dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT);
+        dalloc(&gmY, 64 * 16);
+        GPLHR_HIP_CHECK(hipHostMalloc((void **)&hgm, sizeof(double2) * (pre.steps + 1) * 4 * GM_SLOT,
+                                      hipHostMallocDefault));
+    }
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
     {
         std::vector<double2> e(EYE_N * EYE_N, make_double2(0.0, 0.0));
@@ -608,9 +837,9 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         launch_randn(st, n, b, opt.seed, wd.Z, smax);
     if (mixed) {
         launch_c128_to_c64(st, n, b, wd.Z, smax, wf.Z, smax);
-        init_from_Z<float2>(b);
+        if (eig) init_eig<float2>(); else init_from_Z<float2>(b);
     } else {
-        init_from_Z<double2>(b);
+        if (eig) init_eig<double2>(); else init_from_Z<double2>(b);
     }
     if (phase == 0) check<float2>(); else check<double2>();
     checked = true;
@@ -621,6 +850,18 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
 void Ctx::switch_to_fp64() {
     const int offP = smax - b;
     launch_c64_to_c128(st, n, b, wf.Z, smax, wd.Z, smax);
+    if (eig) {
+        // restart Algorithm 3 from the current X = V Rx (P starts empty)
+        std::memcpy(hpin, Rx.data(), (size_t)b * b * sizeof(cd));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(coefY, hpin, (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
+        UpdTerm<double2> t;
+        t.in = wd.Z; t.ld = smax; t.col = 0; t.w = b; t.M = coefY; t.ldm = b;
+        update<double2>(wd.Z, smax, b, 0, b, 0, false, 1, &t);
+        phase = 1;
+        init_eig<double2>();
+        checked = false;
+        return;
+    }
     int w0 = b;
     if (pw > 0) {
         launch_c64_to_c128(st, n, pw, wf.Z + offP, smax, wd.Z + b, smax);
@@ -713,6 +954,8 @@ void Ctx::eigvecs(double2 *X) {
 // explicit instantiations
 template void Ctx::iterate_once<double2>();
 template void Ctx::iterate_once<float2>();
+template void Ctx::update<double2>(double2 *, int, int, int, int, int, bool, int,
+                                   const UpdTerm<double2> *);
 
 }  // namespace gplhr
 namespace gplhr {

@@ -70,9 +70,11 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
 
 // Cholesky-QR factor: given the w-by-w Gram G (column-major, Hermitian),
 // writes Rinv (column-major, upper triangular) with X Rinv orthonormal for
-// X^H X = G.  Diagonal scaling first; a vanishing pivot triggers a diagonal
+// X^H X = G, and, when Rout is not null, the factor R = Rinv^{-1} itself
+// (G = R^H R).  Diagonal scaling first; a vanishing pivot triggers a diagonal
 // shift and increments status[0].
-void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status);
+void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status,
+                      double2 *Rout = nullptr);
 
 // Out(:, 0:w) = rowscale .* In(:, 0:w)  (rowscale complex per row; null = copy)
 template <typename T>

@@ -737,7 +737,7 @@ template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, in
 // Cholesky-QR factor (one workgroup, w <= 64)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G, double2 *Rinv,
-                                                        int *status) {
+                                                        int *status, double2 *Rout) {
     // A holds the scaled Gram; its upper triangle becomes R (A = R^H R) and
     // its strict lower triangle then receives R^{-1} transposed (the diagonal
     // of R^{-1} goes to dinv).
@@ -821,14 +821,21 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         else if (i < j)
             v = A[j + i * w];
         Rinv[e] = make_double2(v.x * dsc[i], v.y * dsc[i]);
+        if (Rout) {
+            // G = D^{-1} R_s^H R_s D^{-1}: R = R_s D^{-1}
+            double2 r = make_double2(0.0, 0.0);
+            if (i <= j) r = make_double2(A[i + j * w].x / dsc[j], A[i + j * w].y / dsc[j]);
+            Rout[e] = r;
+        }
     }
     __syncthreads();
     if (tid == 0 && flag > 0 && status) atomicAdd(status, flag);
 }
 
-void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status) {
+void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status,
+                      double2 *Rout) {
     if (w < 1 || w > 48) throw Error(-1, "cholqr: width out of range");
-    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status);
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status, Rout);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 

@@ -334,6 +334,32 @@ Mat tri_eigvecs(const Mat &T) {
     return V;
 }
 
+bool harmonic_eig(const Mat &K, const Mat &Gm, int nkeep, Mat &Ybar) {
+    const int s = K.r;
+    // eigenvectors of (K + sigma Gm, Gm) are those of M = K^{-1} Gm, with
+    // eigenvalues 1/(lambda - sigma): order by |.| descending in the Schur form
+    // and take the eigenvectors of its leading triangular block
+    Mat M;
+    if (!lu_solve(K, Gm, M)) return false;
+    Mat Y;
+    if (!schur(M, Y)) return false;
+    const int nc = std::min(nkeep, s);
+    reorder_desc_abs(M, Y, nc);
+    Mat Tl(nc, nc);
+    for (int j = 0; j < nc; ++j)
+        for (int i = 0; i <= j; ++i) Tl(i, j) = M(i, j);
+    const Mat E = tri_eigvecs(Tl);
+    Ybar = Mat(s, nc);
+    for (int j = 0; j < nc; ++j)
+        for (int l = 0; l <= j; ++l) {
+            const cd e = E(l, j);
+            for (int i = 0; i < s; ++i) Ybar(i, j) += Y(i, l) * e;
+        }
+    for (const cd &v : Ybar.a)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return false;
+    return true;
+}
+
 Mat tri_solve_upper(const Mat &U, const Mat &B) {
     const int n = U.r;
     Mat X = B;

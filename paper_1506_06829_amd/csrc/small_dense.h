@@ -66,6 +66,12 @@ struct SrrResult {
 bool harmonic_srr(const Mat &K, const Mat &Gm, std::complex<double> sigma, int b, int nkeep,
                   SrrResult &out);
 
+// Projected eigenproblem of the eigenvector form (Algorithm 3): eigenvectors
+// of (F, G) = (K + sigma Gm, Gm), ordered by |lambda - sigma| ascending; the
+// first nkeep (at most s) are returned as columns of Ybar (unit norm).
+// Returns false when K is singular.
+bool harmonic_eig(const Mat &K, const Mat &Gm, int nkeep, Mat &Ybar);
+
 // M_A, M_B from R_A, R_B with the diagonal G1, G2 of eqs. G1_fix / G2_fix.
 void q_free_factors(const Mat &RA, const Mat &RB, Mat &MA, Mat &MB);
 

@@ -23,7 +23,7 @@ OK, NOT_CONVERGED = 0, 1
 _STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_ALLOC", -3: "ERR_HIP",
            -4: "ERR_BREAKDOWN", -5: "ERR_SINGULAR_SHIFT", -6: "ERR_NUMERIC",
            -7: "ERR_NOT_SIMPLE", -8: "ERR_STATE"}
-PRECOND = {"none": 0, "diag": 1, "jacobi": 2}
+PRECOND = {"none": 0, "diag": 1, "jacobi": 2, "gmres": 3}
 
 
 class GplhrError(RuntimeError):
@@ -38,7 +38,8 @@ class _Csr(ctypes.Structure):
 
 
 class _Precond(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("sweeps", ctypes.c_int), ("omega", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("sweeps", ctypes.c_int), ("omega", ctypes.c_double),
+                ("steps", ctypes.c_int), ("inner", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):
@@ -47,7 +48,8 @@ class _Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
                 ("switch_tol", ctypes.c_double), ("stall_window", ctypes.c_int),
                 ("timing", ctypes.c_int), ("proj_before_T", ctypes.c_int),
-                ("locking", ctypes.c_int), ("m_max", ctypes.c_int)]
+                ("locking", ctypes.c_int), ("m_max", ctypes.c_int),
+                ("algorithm", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -63,7 +65,8 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
-           "gplhr_get_eigvecs", "gplhr_eig_backward", "gplhr_get_stats", "gplhr_destroy",
+           "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
+           "gplhr_destroy",
            "gplhr_last_error", "gplhr_spmm", "gplhr_gram"]
 
 
@@ -88,6 +91,8 @@ def lib():
     L.gplhr_get_schur.restype = i32
     L.gplhr_get_eigvecs.argtypes = [vp, vp]
     L.gplhr_get_eigvecs.restype = i32
+    L.gplhr_get_eig.argtypes = [vp, vp, vp, vp, vp]
+    L.gplhr_get_eig.restype = i32
     L.gplhr_eig_backward.argtypes = [vp, vp, vp, vp]
     L.gplhr_eig_backward.restype = i32
     L.gplhr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
@@ -156,7 +161,8 @@ class Solver:
                  max_iter: int = 500, m: int = 1, p_mode: str = "thick",
                  V0: Optional[torch.Tensor] = None, seed: int = 1, timing: bool = False,
                  switch_tol: float = 1e-5, stall_window: int = 20, stream=None,
-                 proj_before_T: bool = True, locking: bool = False, m_max: int = 20):
+                 proj_before_T: bool = True, locking: bool = False, m_max: int = 20,
+                 steps: int = 2, inner: str = "jacobi", algorithm: str = "schur"):
         L = lib()
         self.n, self.k = A.n, k
         self.block = block or k
@@ -181,7 +187,10 @@ class Solver:
         opt.proj_before_T = 1 if proj_before_T else 0
         opt.locking = 1 if locking else 0
         opt.m_max = m_max
-        pre = _Precond(PRECOND[precond], sweeps, omega)
+        opt.algorithm = {"schur": 0, "eig": 1}[algorithm]
+        self.algorithm = algorithm
+        # precond "gmres": `steps` block GMRES steps right-preconditioned by `inner`
+        pre = _Precond(PRECOND[precond], sweeps, omega, steps, PRECOND[inner])
         a = A._c()
         b = B._c() if B is not None else None
         h = ctypes.c_void_p()
@@ -208,6 +217,23 @@ class Solver:
         _check(lib().gplhr_get_schur(self.h, _ptr(V), _ptr(Q), RA.ctypes.data, RB.ctypes.data,
                                      lam.ctypes.data, rho.ctypes.data), self.h)
         return dict(V=V, Q=Q, RA=RA, RB=RB, lam=lam, rho=rho)
+
+    def eig(self, want_vectors: bool = True):
+        """GPLHR-EIG output: X, Lambda_A, Lambda_B (diagonals), lam = LA / LB, rho."""
+        n, k = self.n, self.k
+        X = torch.empty((n, k), dtype=torch.complex128, device="cuda") if want_vectors else None
+        LA = np.zeros(k, dtype=np.complex128)
+        LB = np.zeros(k, dtype=np.complex128)
+        rho = np.zeros(k, dtype=np.float64)
+        _check(lib().gplhr_get_eig(self.h, _ptr(X), LA.ctypes.data, LB.ctypes.data,
+                                   rho.ctypes.data), self.h)
+        return dict(X=X, LA=LA, LB=LB, lam=LA / LB, rho=rho)
+
+    def lam(self) -> np.ndarray:
+        """Current eigenvalue approximations of the k leading columns."""
+        if self.algorithm == "eig":
+            return self.eig(want_vectors=False)["lam"]
+        return self.schur(want_vectors=False)["lam"]
 
     def eigvecs(self) -> torch.Tensor:
         X = torch.empty((self.n, self.k), dtype=torch.complex128, device="cuda")
@@ -277,7 +303,7 @@ class GPLHREig(torch.autograd.Function):
         st, _, res = s.iterate()
         if st != OK:
             raise GplhrError(NOT_CONVERGED, f"forward solve did not converge (residual {res:.3e})")
-        lam = s.schur(want_vectors=False)["lam"]
+        lam = s.lam()
         ctx.solver = s
         ctx.nnzA = A.nnz
         ctx.nnzB = None if B is None else B.nnz

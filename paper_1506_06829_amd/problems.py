@@ -172,12 +172,14 @@ class Problem:
     sigma: complex
     k: int
     block: int
-    precond: str            # "diag" or "jacobi"
+    precond: str            # "diag", "jacobi" or "gmres"
     sweeps: int = 0
     omega: float = 0.0
     precision: str = "fp64"  # "fp64" or "mixed"
     tol: float = 1e-10
     V0: np.ndarray = field(default=None, repr=False)
+    steps: int = 0           # "gmres": block steps
+    inner: str = "jacobi"    # "gmres": inner right preconditioner
 
     @property
     def n(self) -> int:
@@ -202,6 +204,10 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
     d1  diagonally dominant pencil (see diag_dominant_pencil), n=262144,
         B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T=diag(C)^-1, complex128
     d1m d1 in mixed precision
+    d2  diagonally dominant pencil with coupling 4 (diagonal T alone converges
+        slowly), n=262144, B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T = 2 block
+        GMRES steps right-preconditioned by 3 Jacobi sweeps (omega=0.7), complex128
+    d2m d2 in mixed precision
 
     ``scale`` overrides the grid size N (stencils) or n (random pencil) to give
     a smaller instance of the same family.
@@ -230,4 +236,10 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
         A, B = diag_dominant_pencil(n, 0)
         return _with_v0(Problem(name, A, B, n / 2 + 0.3j, 10, 10, "diag",
                                 precision="fp64" if name == "d1" else "mixed"))
+    if name in ("d2", "d2m"):
+        n = scale or 262144
+        A, B = diag_dominant_pencil(n, 0, coupling=4.0)
+        return _with_v0(Problem(name, A, B, n / 2 + 0.3j, 10, 10, "gmres", 3, 0.7,
+                                precision="fp64" if name == "d2" else "mixed",
+                                steps=2, inner="jacobi"))
     raise ValueError(f"unknown workload {name!r}")

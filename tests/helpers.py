@@ -26,6 +26,8 @@ def gpu_solver(p, precision=None, V0=True, **kw):
     v0 = torch.as_tensor(p.V0).to("cuda") if V0 else None
     opts = dict(precond=p.precond, sweeps=p.sweeps or 3, omega=p.omega or 0.7,
                 precision=precision or p.precision, V0=v0)
+    if p.precond == "gmres":
+        opts.update(steps=p.steps, inner=p.inner)
     opts.update(kw)
     return G.Solver(A, B, p.sigma, p.k, p.block, **opts), A, B
 
@@ -33,9 +35,9 @@ def gpu_solver(p, precision=None, V0=True, **kw):
 def gpu_trajectory(p, its, precision=None, **kw):
     """Rayleigh-Ritz eigenvalues after 0..its iterations on the GPU."""
     s, _, _ = gpu_solver(p, precision=precision, tol=0.0, **kw)
-    lams = [s.schur(want_vectors=False)["lam"]]
+    lams = [s.lam()]
     for _ in range(its):
         s.iterate(1)
-        lams.append(s.schur(want_vectors=False)["lam"])
+        lams.append(s.lam())
     s.close()
     return lams

@@ -54,8 +54,27 @@ def test_argument_errors_without_device_work():
     assert L.gplhr_iterate(None, 1, None, None) == -1
 
 
-def test_ctypes_structs_match_header():
+def test_ctypes_structs_match_header(tmp_path):
+    # a C probe compiled against the header prints sizeof and every field
+    # offset; the ctypes mirrors of the binding must agree field by field
+    import subprocess
     from paper_1506_06829_amd import gplhr
-    # int64 n, nnz + three pointers
-    assert ctypes.sizeof(gplhr._Csr) == 40
-    assert ctypes.sizeof(gplhr._Precond) == 16
+    structs = {"gplhr_csr": gplhr._Csr, "gplhr_precond": gplhr._Precond,
+               "gplhr_options": gplhr._Options, "gplhr_stats": gplhr._Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gplhr.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", str(ROOT / "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

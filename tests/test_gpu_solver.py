@@ -53,6 +53,60 @@ def test_trajectory_parity_variants(device, variant):
         assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, (variant, i)
 
 
+def _with_gmres(p, steps=2, inner="jacobi"):
+    p.precond, p.steps, p.inner, p.sweeps, p.omega = "gmres", steps, inner, 3, 0.7
+    return p
+
+
+@pytest.mark.parametrize("name,scale,steps,inner", [("c4", 600, 2, "jacobi"),
+                                                    ("c2", 12, 3, "diag"),
+                                                    ("d2", 3000, 2, "jacobi")])
+def test_trajectory_parity_block_gmres(device, name, scale, steps, inner):
+    # T = block GMRES(steps) right-preconditioned by `inner` (Section 4)
+    p = _with_gmres(problems.config(name, scale), steps, inner)
+    its = 5
+    gpu = gpu_trajectory(p, its, precision="fp64")
+    ref = O.solve_problem(p, tol=0.0, maxit=its).lam_history
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, (name, i)
+
+
+@pytest.mark.parametrize("name,scale,p_mode", [("c4", 600, "thick"), ("d1", 3000, "thick"),
+                                              ("d1", 3000, "lobpcg"), ("d1", 3000, "none"),
+                                              ("c2", 12, "thick"), ("c1", None, "thick")])
+def test_trajectory_parity_eig(device, name, scale, p_mode):
+    # GPLHR-EIG (Algorithm 3): Rayleigh quotients of the eigenvector iterates
+    p = problems.config(name, scale)
+    its = 5
+    gpu = gpu_trajectory(p, its, precision="fp64", algorithm="eig", p_mode=p_mode)
+    ref = O.solve_problem(p, tol=0.0, maxit=its, algorithm="eig", p_mode=p_mode).lam_history
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, (name, p_mode, i)
+
+
+@pytest.mark.parametrize("name,precision", [("d1", "fp64"), ("d1", "mixed"), ("d2", "fp64")])
+def test_converged_parity_eig_small(device, name, precision):
+    p = problems.config(name, 3000)
+    s, _, _ = gpu_solver(p, precision=precision, max_iter=100, algorithm="eig")
+    st, nconv, res = s.iterate()
+    out = s.eig()
+    s.close()
+    assert st == 0 and nconv == p.k and res <= 1e-10
+    ref = O.solve_problem(p, tol=1e-10, maxit=100, algorithm="eig")
+    assert ref.converged
+    assert match_err(out["lam"][:p.k], ref.lam[:p.k]) < 1e-10
+    # the outputs form a partial eigendecomposition A X Lambda_B = B X Lambda_A
+    X = out["X"].cpu().numpy()
+    A, B = p.A.to_scipy(), p.B.to_scipy()
+    np.testing.assert_allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-12)
+    np.testing.assert_allclose(np.einsum("ij,ij->j", X.conj(), A @ X), out["LA"],
+                               rtol=1e-12, atol=1e-12 * np.abs(out["LA"]).max())
+    np.testing.assert_allclose(np.einsum("ij,ij->j", X.conj(), B @ X), out["LB"], rtol=1e-12)
+    rel = np.linalg.norm(A @ X - (B @ X) * out["lam"][None, :], axis=0) / np.linalg.norm(A @ X, axis=0)
+    assert np.all(rel <= 1.01e-10)
+    np.testing.assert_allclose(rel, out["rho"], rtol=1e-3, atol=1e-14)
+
+
 @pytest.mark.parametrize("seed,p_mode", [(2, "thick"), (0, "lobpcg")])
 def test_locking_trajectory_parity(device, seed, p_mode):
     # soft locking with adaptive m: locked count, depth and eigenvalues after
@@ -96,9 +150,10 @@ def test_trajectory_parity_full_size_64cube(device):
         assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, i
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_converged_parity_small(device, precision):
-    p = problems.config("d1", 3000)
+@pytest.mark.parametrize("name,precision", [("d1", "fp64"), ("d1", "mixed"),
+                                            ("d2", "fp64"), ("d2", "mixed")])
+def test_converged_parity_small(device, name, precision):
+    p = problems.config(name, 3000)
     s, _, _ = gpu_solver(p, precision=precision, max_iter=100)
     st, nconv, res = s.iterate()
     out = s.schur()
@@ -120,14 +175,18 @@ def _d1_reference():
     return ref.lam
 
 
-@pytest.mark.parametrize("precision,locking", [("fp64", False), ("mixed", False),
-                                               ("fp64", True), ("mixed", True)])
-def test_converged_parity_full_size(device, precision, locking):
-    # n = 262144, k = 10, B = diag U[1,2], diagonal preconditioner
+@pytest.mark.parametrize("precision,kw", [("fp64", {}), ("mixed", {}),
+                                         ("fp64", dict(locking=True)),
+                                         ("mixed", dict(locking=True)),
+                                         ("fp64", dict(algorithm="eig")),
+                                         ("mixed", dict(algorithm="eig"))])
+def test_converged_parity_full_size(device, precision, kw):
+    # n = 262144, k = 10, B = diag U[1,2], diagonal preconditioner; the
+    # eigenvalues are those of the FP64 oracle (Schur form) whatever the form
     p = problems.config("d1")
-    s, _, _ = gpu_solver(p, precision=precision, max_iter=100, locking=locking)
+    s, _, _ = gpu_solver(p, precision=precision, max_iter=100, **kw)
     st, nconv, res = s.iterate()
-    lam = s.schur(want_vectors=False)["lam"]
+    lam = s.lam()
     s.close()
     assert st == 0 and res <= 1e-10
     assert match_err(lam[:p.k], _d1_reference()[:p.k]) < 1e-10
@@ -195,6 +254,28 @@ def test_error_paths(device):
         G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5, 3, 2)
     with pytest.raises(G.GplhrError):
         G.Solver(G.DeviceCsr.from_host(problems.diag_csr(np.arange(10.0) + 1)), None, 0.5, 4, 4)
+    # block GMRES: steps * block above 64, or an inner kind that is not basic
+    with pytest.raises(G.GplhrError) as e:
+        G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 8, precond="gmres", steps=9)
+    assert e.value.status == -1
+    with pytest.raises(G.GplhrError) as e:
+        G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, precond="gmres", inner="gmres")
+    assert e.value.status == -1
+    # output of the other form
+    s = G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, precond="diag", max_iter=1,
+                 algorithm="eig")
+    with pytest.raises(G.GplhrError) as e:
+        s.schur()
+    assert e.value.status == -8
+    s.close()
+    s = G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, precond="diag", max_iter=1)
+    with pytest.raises(G.GplhrError) as e:
+        s.eig()
+    assert e.value.status == -8
+    s.close()
+    with pytest.raises(G.GplhrError) as e:
+        G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, algorithm="eig", locking=True)
+    assert e.value.status == -1
     # backward before convergence
     s = G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, precond="diag", max_iter=1)
     with pytest.raises(G.GplhrError) as e:
@@ -203,7 +284,8 @@ def test_error_paths(device):
     s.close()
 
 
-def test_backward_matches_dense_derivatives(device):
+@pytest.mark.parametrize("algorithm", ["schur", "eig"])
+def test_backward_matches_dense_derivatives(device, algorithm):
     import torch
     from paper_1506_06829_amd import gplhr as G
     n, k = 700, 4
@@ -213,7 +295,8 @@ def test_backward_matches_dense_derivatives(device):
     valA = dA.val.clone().requires_grad_(True)
     valB = dB.val.clone().requires_grad_(True)
     lam = G.GPLHREig.apply(valA, valB, dA, dB, sigma, k,
-                           dict(precond="diag", block=k, tol=1e-12, max_iter=200))
+                           dict(precond="diag", block=k, tol=1e-12, max_iter=200,
+                                algorithm=algorithm))
     loss = torch.sum(torch.abs(lam - sigma) ** 2)
     loss.backward()
     gA, gB = valA.grad.cpu().numpy(), valB.grad.cpu().numpy()

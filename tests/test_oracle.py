@@ -260,6 +260,109 @@ def test_locking_without_converged_pairs_is_the_plain_iteration():
         assert np.array_equal(a, b)
 
 
+def _small_c(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rand_c(rng, n, n) + 4 * np.eye(n)
+    return sp.csr_matrix(A), rng
+
+
+def test_block_gmres_exact_on_full_krylov_space():
+    # s a >= n: the block Krylov space is the whole space, so one call is C^{-1}
+    n, a = 24, 3
+    C, rng = _small_c(n, 21)
+    R = rand_c(rng, n, a)
+    for inner in ("identity", "diag", "jacobi"):
+        T = O.make_preconditioner(C, "gmres", sweeps=2, omega=0.7, steps=n // a, inner=inner)
+        W = T(R)
+        ref = np.linalg.solve(C.toarray(), R)
+        assert np.abs(W - ref).max() < 1e-9 * np.abs(ref).max(), inner
+
+
+@pytest.mark.parametrize("steps,inner", [(1, "diag"), (3, "jacobi"), (4, "identity")])
+def test_block_gmres_minimises_over_monomial_krylov_basis(steps, inner):
+    # brute force on the explicit basis [R, (CM)R, ..., (CM)^{s-1}R]: every
+    # column of R - C W is the least-squares residual over that whole space
+    n, a = 60, 2
+    C, rng = _small_c(n, 22)
+    R = rand_c(rng, n, a)
+    M = O.make_preconditioner(C, inner, sweeps=2, omega=0.7)
+    blocks = [R]
+    for _ in range(steps - 1):
+        blocks.append(C @ M(blocks[-1]))
+    K = np.hstack(blocks)
+    CMK = C @ M(K)
+    Y = np.linalg.lstsq(CMK, R, rcond=None)[0]
+    ref = M(K @ Y)
+    W = O.make_preconditioner(C, "gmres", sweeps=2, omega=0.7, steps=steps, inner=inner)(R)
+    assert np.abs(W - ref).max() < 1e-9 * np.abs(ref).max()
+    # the residual decreases with the number of steps (nested Krylov spaces)
+    if steps > 1:
+        W1 = O.make_preconditioner(C, "gmres", sweeps=2, omega=0.7, steps=steps - 1,
+                                   inner=inner)(R)
+        assert np.linalg.norm(R - C @ W) <= np.linalg.norm(R - C @ W1) * (1 + 1e-12)
+
+
+def test_gplhr_with_block_gmres_preconditioner_matches_dense():
+    # the stronger T of Section 4 inside Algorithm 2, on a coupled pencil where
+    # the diagonal alone is weak
+    n, k = 800, 4
+    A, B = problems.diag_dominant_pencil(n, 0, coupling=4.0)
+    As, Bs = A.to_scipy(), B.to_scipy()
+    sigma = n / 2 + 0.3j
+    C = (As - sigma * Bs).tocsr()
+    V0 = problems.start_block(n, k)
+    T = O.make_preconditioner(C, "gmres", sweeps=3, omega=0.7, steps=2, inner="jacobi")
+    r = O.gplhr(As, Bs, sigma, k, V0, T, tol=1e-11, maxit=100)
+    assert r.converged
+    ref = nearest(sla.eigvals(As.toarray(), Bs.toarray()), sigma, k)
+    assert match_err(r.lam[:k], ref) < 1e-9
+    rj = O.gplhr(As, Bs, sigma, k, V0, O.make_preconditioner(C, "jacobi", 3, 0.7), tol=1e-11,
+                 maxit=100)
+    assert r.iterations < rj.iterations
+
+
+@pytest.mark.parametrize("seed,std,m,p_mode", [(0, False, 1, "thick"), (1, True, 1, "thick"),
+                                              (3, False, 2, "lobpcg"), (4, False, 1, "none")])
+def test_gplhr_eig_small_pencils_match_zggev(seed, std, m, p_mode):
+    # Algorithm 3: unit eigenvector approximations whose Rayleigh quotients
+    # converge to the eigenvalues nearest sigma (LAPACK zggev).  (The
+    # LOBPCG-style P can oscillate without converging -- seed 2 does -- as the
+    # non-converged entries of Table 2 show for that choice.)
+    rng = np.random.default_rng(seed)
+    n, k = 40, 3
+    A = rand_c(rng, n, n) + 3 * np.eye(n)
+    B = None if std else np.eye(n) + 0.3 * rand_c(rng, n, n)
+    sigma = complex(rng.normal(), rng.normal())
+    Bm = np.eye(n) if std else B
+    C = sp.csr_matrix(A - sigma * Bm)
+    r = O.gplhr_eig(sp.csr_matrix(A), None if std else sp.csr_matrix(B), sigma, k,
+                    rand_c(rng, n, k), O.make_preconditioner(C, "exact"), m=m, tol=1e-11,
+                    maxit=60, p_mode=p_mode)
+    assert r.converged
+    ref = nearest(sla.eigvals(A, Bm), sigma, k)
+    assert match_err(r.lam[:k], ref) < 1e-9
+    X = r.X[:, :k]
+    np.testing.assert_allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-13)
+    # A X Lambda_B = B X Lambda_A (partial eigendecomposition) to the tolerance
+    res = A @ X * r.beta[None, :k] - Bm @ X * r.alpha[None, :k]
+    assert np.linalg.norm(res) < 1e-9 * np.linalg.norm(A @ X)
+
+
+def test_gplhr_eig_full_trial_space_is_exact_after_one_iteration():
+    rng = np.random.default_rng(9)
+    b = 4
+    n = 3 * b
+    A = rand_c(rng, n, n) + 2 * np.eye(n)
+    B = np.eye(n) + 0.2 * rand_c(rng, n, n)
+    sigma = 0.3 + 0.1j
+    C = sp.csr_matrix(A - sigma * B)
+    r = O.gplhr_eig(sp.csr_matrix(A), sp.csr_matrix(B), sigma, b, rand_c(rng, n, b),
+                    O.make_preconditioner(C, "identity"), tol=0.0, maxit=1)
+    assert r.iterations == 1
+    assert match_err(r.lam[:b], nearest(sla.eigvals(A, B), sigma, b)) < 1e-10
+    assert np.max(r.rho[:b]) < 1e-11
+
+
 def test_random_pencil_family_matches_zggev():
     A, B = problems.random_pencil(200, seed=0)
     As, Bs = A.to_scipy(), B.to_scipy()
