@@ -143,11 +143,24 @@ typedef struct {
                            projected pencil nearest sigma.  Not combined with
                            locking; in MIXED precision P restarts empty when the
                            FP64 phase begins                                     */
+    /* Deflation (the remarks after Algorithm 2): with converged bases V1, Q1 of
+     * k1 right/left generalized Schur vectors (for instance V and Q of an
+     * earlier handle), iterate on the deflated pair
+     * ((I - Q1 Q1^H) A (I - V1 V1^H), (I - Q1 Q1^H) B (I - V1 V1^H)), or on
+     * (I - V1 V1^H) A (I - V1 V1^H) for B = I, to obtain further Schur
+     * vectors.  The trial basis is kept orthogonal to V1 (V0 and every output
+     * of T are projected).  Device n-by-defl_k complex128 row-major (ld =
+     * defl_k) with orthonormal columns, copied during gplhr_create; defl_Q is
+     * ignored for B = I.  0 <= defl_k <= 64; the backward pass is not
+     * available for a deflated handle.                                          */
+    const void *defl_V;
+    const void *defl_Q;
+    int defl_k;
 } gplhr_options;
 
 /* Fill *opt with defaults: FP64, tol 1e-10, max_iter 500, arnoldi_m 1, thick P,
  * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0,
- * proj_before_T 1, locking 0, m_max 20, algorithm SCHUR. */
+ * proj_before_T 1, locking 0, m_max 20, algorithm SCHUR, no deflation. */
 void gplhr_default_options(gplhr_options *opt);
 
 /* Set up the operator C = A - sigma B on the union sparsity pattern, its

@@ -525,6 +525,37 @@ def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
                           lam_history=lam_history)
 
 
+def deflated_pair(A, B, V1: np.ndarray, Q1: Optional[np.ndarray]):
+    """The deflated pair of the remarks after Algorithm 2, formed explicitly
+    (dense, small n only): ((I - Q1 Q1^*) A (I - V1 V1^*), (I - Q1 Q1^*) B (I - V1 V1^*)),
+    or ((I - V1 V1^*) A (I - V1 V1^*), None) for B = I."""
+    L = V1 if B is None else Q1
+
+    def both(M):
+        M = M - L @ (L.conj().T @ M)
+        return M - (M @ V1) @ V1.conj().T
+
+    Ad = both(sp.csr_matrix(A).toarray().astype(complex))
+    Bd = None if B is None else both(sp.csr_matrix(B).toarray().astype(complex))
+    return sp.csr_matrix(Ad), None if Bd is None else sp.csr_matrix(Bd)
+
+
+def gplhr_deflated(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
+                   V1: np.ndarray, Q1: Optional[np.ndarray], **kw) -> GplhrResult:
+    """Further Schur vectors by deflation: Algorithm 2 on ``deflated_pair``.
+
+    Reading (the paper names the deflated pair only): the iteration starts
+    from (I - V1 V1^*) V0 and the preconditioner is followed by
+    (I - V1 V1^*), so that the trial subspace stays orthogonal to the deflated
+    vectors (on span(V1) the deflated pair vanishes identically)."""
+    Ad, Bd = deflated_pair(A, B, V1, Q1)
+
+    def pv(X):
+        return X - V1 @ (V1.conj().T @ X)
+
+    return gplhr(Ad, Bd, sigma, k, pv(V0), lambda R: pv(precond(R)), **kw)
+
+
 def solve_problem(problem, tol: Optional[float] = None, maxit: int = 500, **kw) -> GplhrResult:
     """Run the oracle on a ``problems.Problem`` (inputs only; no method code
     lives there)."""

@@ -57,6 +57,9 @@ void gplhr_default_options(gplhr_options *opt) {
     opt->locking = 0;
     opt->m_max = 20;
     opt->algorithm = GPLHR_ALG_SCHUR;
+    opt->defl_V = nullptr;
+    opt->defl_Q = nullptr;
+    opt->defl_k = 0;
 }
 
 gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B, double sigma_re,
@@ -166,6 +169,7 @@ gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad
     return guard(h, [&]() -> int {
         gplhr::Ctx &c = h->c;
         if (!c.converged) throw gplhr::Error(-8, "gplhr_eig_backward needs a converged handle");
+        if (c.defl_k) throw gplhr::Error(-8, "gplhr_eig_backward is not available for a deflated handle");
         const int64_t n = c.n;
         const int k = c.k;
         hipStream_t st = c.st;

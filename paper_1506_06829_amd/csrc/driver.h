@@ -26,6 +26,7 @@ struct Work {
     T *Z = nullptr, *CZ = nullptr, *BZ = nullptr, *U = nullptr;   // n x smax
     T *R = nullptr, *J1 = nullptr, *J2 = nullptr;                  // n x b
     T *G = nullptr;                    // block GMRES basis, n x (steps+1) b
+    T *Vd = nullptr, *Qd = nullptr;    // deflation bases, n x defl_k
     T *Gz = nullptr, *Gx = nullptr;    // block GMRES temporaries, n x b
 };
 
@@ -58,6 +59,11 @@ struct Ctx {
     BKind bk = B_IDENT;
     bool mixed = false, xcd_remap = false;
     bool eig = false;   // GPLHR-EIG (Algorithm 3) instead of the Schur form
+    int defl_k = 0;     // columns of the deflation bases (0: no deflation)
+    // B Z kept as an explicit block (general sparse B, or any B != I under
+    // deflation); otherwise B Z is Z or diag(B) Z formed on the fly
+    bool bexp() const { return bk == B_SPARSE || (defl_k > 0 && bk == B_DIAG); }
+    template <typename T> const T *bscale() { return (bk == B_DIAG && !bexp()) ? W<T>().bd : nullptr; }
     int phase = 1;
     bool converged = false, checked = false;
 
@@ -135,6 +141,10 @@ struct Ctx {
     void spmm_c(const T *X, int ldx, T *Y, int ldy, int w, int mode, const T *Rhs, int ldr);
     template <typename T>
     void spmm_b(const T *X, int ldx, T *Y, int ldy, int w);
+    template <typename T> void cprod(const T *X, int ldx, T *Y, int ldy, int w);
+    template <typename T> void bprod(const T *X, int ldx, T *Y, int ldy, int w);
+    template <typename T> void deflate_left(T *Y, int ldy, int w);
+    template <typename T> void deflate_right(T *X, int ldx, int col, int w);
     template <typename T> void apply_T(T *dest, int ldd, int dcol, int w);
     template <typename T>
     void apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int w);

@@ -56,8 +56,8 @@ Ctx::~Ctx() {
     dfree(a_rp); dfree(a_ci); dfree(a_val);
     dfree(b_rp); dfree(b_ci); dfree(b_val); dfree(b_val32);
     dfree(bd); dfree(bd32); dfree(dinv); dfree(dinv32); dfree(dw); dfree(dw32);
-    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); }
-    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); }
+    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
+    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
     dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(eye); dfree(coefY); dfree(coefL);
     dfree(M1); dfree(M2); dfree(M1s); dfree(M2s); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
     dfree(dstatus); dfree(xvec); dfree(ucoef); dfree(gmH); dfree(gmY);
@@ -185,6 +185,37 @@ void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy, int wc) {
     spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * wc * sizeof(T);
 }
 
+// Deflation (remarks after Algorithm 2): with converged bases V1, Q1 the
+// iteration runs on ((I - Q1 Q1^H) A (I - V1 V1^H), (I - Q1 Q1^H) B (I - V1 V1^H))
+// (Q1 = V1 for B = I).  The trial basis is kept orthogonal to V1, so the
+// deflated products are the plain ones followed by (I - Q1 Q1^H).
+template <typename T>
+void Ctx::deflate_left(T *Y, int ldy, int wc) {
+    Work<T> &w = W<T>();
+    project<T>(Y, ldy, 0, wc, w.Qd, defl_k, 0, defl_k);
+}
+template <typename T>
+void Ctx::deflate_right(T *X, int ldx, int col, int wc) {
+    Work<T> &w = W<T>();
+    project<T>(X, ldx, col, wc, w.Vd, defl_k, 0, defl_k);
+}
+
+// Y = C X (deflated), for blocks of the trial basis
+template <typename T>
+void Ctx::cprod(const T *X, int ldx, T *Y, int ldy, int wc) {
+    spmm_c<T>(X, ldx, Y, ldy, wc, 0, nullptr, 0);
+    if (defl_k) deflate_left<T>(Y, ldy, wc);
+}
+
+// Y = B X (deflated) when B Z is kept explicitly; nothing otherwise
+template <typename T>
+void Ctx::bprod(const T *X, int ldx, T *Y, int ldy, int wc) {
+    if (!bexp()) return;
+    if (bk == B_SPARSE) spmm_b<T>(X, ldx, Y, ldy, wc);
+    else launch_scale_rows<T>(st, n, wc, X, ldx, W<T>().bd, Y, ldy);
+    if (defl_k) deflate_left<T>(Y, ldy, wc);
+}
+
 // dest = M in for a basic preconditioner kind (NONE, DIAG, JACOBI); wc columns.
 template <typename T>
 void Ctx::apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int wc) {
@@ -306,8 +337,8 @@ template <typename T>
 void Ctx::srr_and_update(int s_cur, int p_cols) {
     Work<T> &w = W<T>();
     const int ld = smax;
-    const T *bsrc = (bk == B_SPARSE) ? w.BZ : w.Z;
-    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+    const T *bsrc = bexp() ? w.BZ : w.Z;
+    const T *bsc = bscale<T>();
     // a8: F1 = U^H (A - sigma B) Z, F2 = U^H B Z   (s_cur x s_cur, FP64)
     gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
     gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
@@ -360,7 +391,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
         t.in = w.CZ;
         update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
-        if (bk == B_SPARSE) {
+        if (bexp()) {
             t.in = w.BZ;
             update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
         }
@@ -409,7 +440,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
     t.in = w.CZ;
     update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
-    if (bk == B_SPARSE) {
+    if (bexp()) {
         t.in = w.BZ;
         update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
     }
@@ -426,11 +457,13 @@ template <typename T>
 void Ctx::init_from_Z(int w0) {
     Work<T> &w = W<T>();
     const int ld = smax;
+    if (defl_k)
+        for (int pass = 0; pass < 2; ++pass) deflate_right<T>(w.Z, ld, 0, w0);
     cholqr<T>(w.Z, ld, 0, w0, 2, nullptr, nullptr);
     for (int c = 0; c < w0; c += b) {
         const int wc = std::min(b, w0 - c);
-        spmm_c<T>(w.Z + c, ld, w.CZ + c, ld, wc, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(w.Z + c, ld, w.BZ + c, ld, wc);
+        cprod<T>(w.Z + c, ld, w.CZ + c, ld, wc);
+        bprod<T>(w.Z + c, ld, w.BZ + c, ld, wc);
     }
     launch_scale_rows<T>(st, n, w0, w.CZ, ld, nullptr, w.U, ld);
     cholqr<T>(w.U, ld, 0, w0, 2, nullptr, nullptr);
@@ -445,7 +478,7 @@ template <typename T>
 void Ctx::eig_orthonormalise() {
     Work<T> &w = W<T>();
     const int ld = smax;
-    T *bz = (bk == B_SPARSE) ? w.BZ : nullptr;
+    T *bz = bexp() ? w.BZ : nullptr;
     const size_t bb = (size_t)b * b;
     for (int p = 0; p < 2; ++p) {
         gram<T>(w.Z, ld, b, w.Z, ld, b, nullptr, g0);
@@ -478,8 +511,10 @@ void Ctx::eig_orthonormalise() {
 template <typename T>
 void Ctx::init_eig() {
     Work<T> &w = W<T>();
-    spmm_c<T>(w.Z, smax, w.CZ, smax, b, 0, nullptr, 0);
-    if (bk == B_SPARSE) spmm_b<T>(w.Z, smax, w.BZ, smax, b);
+    if (defl_k)
+        for (int pass = 0; pass < 2; ++pass) deflate_right<T>(w.Z, smax, 0, b);
+    cprod<T>(w.Z, smax, w.CZ, smax, b);
+    bprod<T>(w.Z, smax, w.BZ, smax, b);
     eig_orthonormalise<T>();
     pw = 0;
 }
@@ -499,7 +534,7 @@ void Ctx::iterate_once() {
     T *Z = w.Z, *CZ = w.CZ, *BZ = w.BZ, *U = w.U;
     // left projector basis: Q when B != I, V when B = I (steps 8/10, 15/17)
     const T *Lb = (bk == B_IDENT) ? Z : U;
-    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+    const T *bsc = bscale<T>();
 
     // src block (width ws) -> new block of width a at dst:
     //   R = (A - sigma B) X M_B(., q:) + B X (sigma M_B - M_A)(., q:)   (moff selects
@@ -511,15 +546,18 @@ void Ctx::iterate_once() {
     auto build = [&](int src, int ws, const double2 *m1, const double2 *m2, int moff, int dst) {
         UpdTerm<T> t[2];
         t[0].in = CZ; t[0].ld = ld; t[0].col = src; t[0].w = ws; t[0].M = m1 + moff; t[0].ldm = b;
-        t[1].in = (bk == B_SPARSE) ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = ws;
+        t[1].in = bexp() ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = ws;
         t[1].M = m2 + moff; t[1].ldm = b; t[1].rowscale = bsc;
         update<T>(w.R, b, a, 0, a, 0, false, 2, t);
         if (opt.proj_before_T) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
         apply_T<T>(Z, ld, dst, a);
-        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, dst, a, Z, ld, 0, dst);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (defl_k) deflate_right<T>(Z, ld, dst, a);
+            project<T>(Z, ld, dst, a, Z, ld, 0, dst);
+        }
         cholqr<T>(Z, ld, dst, a, 2, nullptr, nullptr);
-        spmm_c<T>(Z + dst, ld, CZ + dst, ld, a, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(Z + dst, ld, BZ + dst, ld, a);
+        cprod<T>(Z + dst, ld, CZ + dst, ld, a);
+        bprod<T>(Z + dst, ld, BZ + dst, ld, a);
     };
     build(0, b, M1, M2, q * b, offW);                                // W (steps 6-12)
     for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
@@ -527,7 +565,7 @@ void Ctx::iterate_once() {
 
     // step 22: P <- orth(P - [V W S][V W S]^H P), mirrored onto C P (and B P)
     if (pa > 0) {
-        T *bz = (bk == B_SPARSE) ? BZ : nullptr;
+        T *bz = bexp() ? BZ : nullptr;
         if (pos != offPs) {
             // the layout is narrower than the kept one: move P next to S_mc
             // (row-local, so overlapping column ranges are safe)
@@ -565,11 +603,11 @@ template <typename T>
 void Ctx::refresh_products() {
     Work<T> &w = W<T>();
     const int ld = smax, offP = smax - b;
-    spmm_c<T>(w.Z, ld, w.CZ, ld, b, 0, nullptr, 0);
-    if (bk == B_SPARSE) spmm_b<T>(w.Z, ld, w.BZ, ld, b);
+    cprod<T>(w.Z, ld, w.CZ, ld, b);
+    bprod<T>(w.Z, ld, w.BZ, ld, b);
     if (pw > 0) {
-        spmm_c<T>(w.Z + offP, ld, w.CZ + offP, ld, pw, 0, nullptr, 0);
-        if (bk == B_SPARSE) spmm_b<T>(w.Z + offP, ld, w.BZ + offP, ld, pw);
+        cprod<T>(w.Z + offP, ld, w.CZ + offP, ld, pw);
+        bprod<T>(w.Z + offP, ld, w.BZ + offP, ld, pw);
     }
 }
 
@@ -586,8 +624,8 @@ template <typename T>
 void Ctx::check() {
     Work<T> &w = W<T>();
     const int ld = smax;
-    const T *bsrc = (bk == B_SPARSE) ? w.BZ : w.Z;
-    const T *bsc = (bk == B_DIAG) ? w.bd : nullptr;
+    const T *bsrc = bexp() ? w.BZ : w.Z;
+    const T *bsc = bscale<T>();
     gram<T>(w.Z, ld, b, w.CZ, ld, b, nullptr, g0);
     gram<T>(w.Z, ld, b, bsrc, ld, b, bsc, g1);
     const size_t bb = (size_t)b * b;
@@ -649,7 +687,7 @@ void Ctx::check() {
     GPLHR_HIP_CHECK(hipMemcpyAsync(dZr, hpin, bb * sizeof(double2), hipMemcpyHostToDevice, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(dlam, hpin + bb, b * sizeof(double2), hipMemcpyHostToDevice, st));
     const int nblk = launch_resid_partials<T>(st, n, b, w.CZ, ld, w.Z, ld,
-                                              bk == B_SPARSE ? w.BZ : nullptr, ld, bsc,
+                                              bexp() ? w.BZ : nullptr, ld, bsc,
                                               to_d2(sigma), dZr, dlam, part, RESID_BLOCKS);
     launch_reduce_partials(st, part, nblk, b, 1, rnorm, b);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb + b, rnorm, b * sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -788,7 +826,19 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     const size_t blk_s = (size_t)n * smax, blk_b = (size_t)n * b;
     wd.cval = c_val; wd.bval = b_val; wd.bd = bd; wd.dinv = dinv; wd.dw = dw;
     dalloc(&wd.Z, blk_s); dalloc(&wd.CZ, blk_s); dalloc(&wd.U, blk_s);
-    if (bk == B_SPARSE) dalloc(&wd.BZ, blk_s);
+    defl_k = opt.defl_k;
+    if (defl_k < 0 || defl_k > 64) throw Error(-1, "defl_k must be in [0, 64]");
+    if (defl_k) {
+        if (!opt.defl_V || (bk != B_IDENT && !opt.defl_Q))
+            throw Error(-1, "deflation needs V1 (and Q1 when B != I)");
+        if (defl_k + smax > n) throw Error(-1, "defl_k + (m+3)*block exceeds n");
+        const void *q1 = (bk == B_IDENT) ? opt.defl_V : opt.defl_Q;
+        dalloc(&wd.Vd, (size_t)n * defl_k);
+        dalloc(&wd.Qd, (size_t)n * defl_k);
+        GPLHR_HIP_CHECK(hipMemcpyAsync(wd.Vd, opt.defl_V, sizeof(double2) * n * defl_k, hipMemcpyDeviceToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(wd.Qd, q1, sizeof(double2) * n * defl_k, hipMemcpyDeviceToDevice, st));
+    }
+    if (bexp()) dalloc(&wd.BZ, blk_s);
     dalloc(&wd.R, blk_b);
     const bool jac2 = (ik == GPLHR_PRECOND_JACOBI && pre.sweeps > 1);
     const bool gm = (pre.kind == GPLHR_PRECOND_GMRES);
@@ -804,7 +854,13 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         if (dinv) { dalloc(&dinv32, n); launch_c128_to_c64_flat(st, n, dinv, dinv32); wf.dinv = dinv32; }
         if (dw) { dalloc(&dw32, n); launch_c128_to_c64_flat(st, n, dw, dw32); wf.dw = dw32; }
         dalloc(&wf.Z, blk_s); dalloc(&wf.CZ, blk_s); dalloc(&wf.U, blk_s);
-        if (bk == B_SPARSE) dalloc(&wf.BZ, blk_s);
+        if (bexp()) dalloc(&wf.BZ, blk_s);
+        if (defl_k) {
+            dalloc(&wf.Vd, (size_t)n * defl_k);
+            dalloc(&wf.Qd, (size_t)n * defl_k);
+            launch_c128_to_c64_flat(st, (int64_t)n * defl_k, wd.Vd, wf.Vd);
+            launch_c128_to_c64_flat(st, (int64_t)n * defl_k, wd.Qd, wf.Qd);
+        }
         dalloc(&wf.R, blk_b);
         if (jac2) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
         if (gm) { dalloc(&wf.G, blk_g); dalloc(&wf.Gz, blk_b); dalloc(&wf.Gx, blk_b); }

@@ -49,7 +49,8 @@ class _Options(ctypes.Structure):
                 ("switch_tol", ctypes.c_double), ("stall_window", ctypes.c_int),
                 ("timing", ctypes.c_int), ("proj_before_T", ctypes.c_int),
                 ("locking", ctypes.c_int), ("m_max", ctypes.c_int),
-                ("algorithm", ctypes.c_int)]
+                ("algorithm", ctypes.c_int), ("defl_V", ctypes.c_void_p),
+                ("defl_Q", ctypes.c_void_p), ("defl_k", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -162,11 +163,12 @@ class Solver:
                  V0: Optional[torch.Tensor] = None, seed: int = 1, timing: bool = False,
                  switch_tol: float = 1e-5, stall_window: int = 20, stream=None,
                  proj_before_T: bool = True, locking: bool = False, m_max: int = 20,
-                 steps: int = 2, inner: str = "jacobi", algorithm: str = "schur"):
+                 steps: int = 2, inner: str = "jacobi", algorithm: str = "schur",
+                 deflate: Optional[tuple] = None):
         L = lib()
         self.n, self.k = A.n, k
         self.block = block or k
-        self._keep = (A, B, V0)
+        self._keep = (A, B, V0, deflate)
         opt = _Options()
         L.gplhr_default_options(ctypes.byref(opt))
         opt.precision = {"fp64": 0, "mixed": 1}[precision]
@@ -188,6 +190,15 @@ class Solver:
         opt.locking = 1 if locking else 0
         opt.m_max = m_max
         opt.algorithm = {"schur": 0, "eig": 1}[algorithm]
+        if deflate is not None:
+            # (V1, Q1): converged Schur bases to deflate (Q1 may be None for B = I)
+            V1, Q1 = deflate
+            for t in (V1, Q1):
+                if t is not None:
+                    assert t.dtype == torch.complex128 and t.is_contiguous() and t.shape[0] == A.n
+            opt.defl_V = V1.data_ptr()
+            opt.defl_Q = Q1.data_ptr() if Q1 is not None else None
+            opt.defl_k = V1.shape[1]
         self.algorithm = algorithm
         # precond "gmres": `steps` block GMRES steps right-preconditioned by `inner`
         pre = _Precond(PRECOND[precond], sweeps, omega, steps, PRECOND[inner])

@@ -107,6 +107,72 @@ def test_converged_parity_eig_small(device, name, precision):
     np.testing.assert_allclose(rel, out["rho"], rtol=1e-3, atol=1e-14)
 
 
+def _half(p, kk):
+    """The same workload asking for kk pairs with block kk."""
+    p.k = p.block = kk
+    p.V0 = np.ascontiguousarray(p.V0[:, :kk])
+    return p
+
+
+def test_deflation_trajectory_parity(device):
+    # deflation (remarks after Algorithm 2) with V1, Q1 from the oracle
+    import torch
+    p = _half(problems.config("d1", 3000), 5)
+    r1 = O.solve_problem(p, tol=1e-12, maxit=100)
+    assert r1.converged
+    A, B = p.A.to_scipy(), p.B.to_scipy()
+    C = (A - p.sigma * B).tocsr()
+    its = 5
+    ref = O.gplhr_deflated(A, B, p.sigma, p.k, p.V0, O.make_preconditioner(C, "diag"),
+                           r1.V, r1.Q, tol=0.0, maxit=its).lam_history
+    V1 = torch.as_tensor(np.ascontiguousarray(r1.V)).to("cuda")
+    Q1 = torch.as_tensor(np.ascontiguousarray(r1.Q)).to("cuda")
+    gpu = gpu_trajectory(p, its, precision="fp64", deflate=(V1, Q1))
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        assert match_err(a[:p.k], b[:p.k]) < FP64_TRAJ_TOL, i
+
+
+def _deflated_pairs(p, precision, **kw):
+    """Two GPU runs of k/2 pairs each, the second on the deflated pair."""
+    s1, _, _ = gpu_solver(p, precision=precision, max_iter=100, **kw)
+    assert s1.iterate()[0] == 0
+    o1 = s1.schur()
+    s1.close()
+    s2, _, _ = gpu_solver(p, precision=precision, max_iter=100, deflate=(o1["V"], o1["Q"]), **kw)
+    st, _, res = s2.iterate()
+    o2 = s2.schur()
+    s2.close()
+    assert st == 0 and res <= 1e-10
+    return o1, o2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deflation_finds_the_next_pairs_small(device, precision):
+    p = _half(problems.config("d1", 3000), 5)
+    o1, o2 = _deflated_pairs(p, precision)
+    ref = O.solve_problem(problems.config("d1", 3000), tol=1e-10, maxit=100)
+    assert ref.converged
+    both = np.concatenate([o1["lam"], o2["lam"]])
+    assert match_err(both, ref.lam[:10]) < 1e-10
+    # [V1 V2] orthonormal, and a partial generalized Schur form of (A, B)
+    V = np.hstack([o1["V"].cpu().numpy(), o2["V"].cpu().numpy()])
+    Q = np.hstack([o1["Q"].cpu().numpy(), o2["Q"].cpu().numpy()])
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(10), atol=1e-10)
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(10), atol=1e-10)
+    A, B = p.A.to_scipy(), p.B.to_scipy()
+    for M in (A, B):
+        R = Q.conj().T @ (M @ V)
+        assert np.abs(np.tril(R, -1)).max() < 1e-8 * np.abs(R).max()
+
+
+def test_deflation_full_size(device):
+    # n = 262144: 5 + 5 pairs by deflation equal the 10 pairs of the oracle
+    p = _half(problems.config("d1"), 5)
+    o1, o2 = _deflated_pairs(p, "fp64")
+    both = np.concatenate([o1["lam"], o2["lam"]])
+    assert match_err(both, _d1_reference()[:10]) < 1e-10
+
+
 @pytest.mark.parametrize("seed,p_mode", [(2, "thick"), (0, "lobpcg")])
 def test_locking_trajectory_parity(device, seed, p_mode):
     # soft locking with adaptive m: locked count, depth and eigenvalues after
@@ -275,6 +341,14 @@ def test_error_paths(device):
     s.close()
     with pytest.raises(G.GplhrError) as e:
         G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, algorithm="eig", locking=True)
+    assert e.value.status == -1
+    # deflation: too many columns, missing Q1 for B != I
+    import torch as _t
+    Bd = problems.diag_csr(np.ones(n))
+    V1 = _t.zeros((n, 2), dtype=_t.complex128, device="cuda")
+    with pytest.raises(G.GplhrError) as e:
+        G.Solver(G.DeviceCsr.from_host(Ad), G.DeviceCsr.from_host(Bd), 0.5 + 0.1j, 2, 2,
+                 deflate=(V1, None))
     assert e.value.status == -1
     # backward before convergence
     s = G.Solver(G.DeviceCsr.from_host(Ad), None, 0.5 + 0.1j, 2, 2, precond="diag", max_iter=1)

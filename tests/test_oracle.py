@@ -363,6 +363,38 @@ def test_gplhr_eig_full_trial_space_is_exact_after_one_iteration():
     assert np.max(r.rho[:b]) < 1e-11
 
 
+@pytest.mark.parametrize("seed,std", [(0, False), (1, True)])
+def test_deflation_yields_the_next_schur_vectors(seed, std):
+    # deflation (remarks after Algorithm 2): GPLHR on the deflated pair finds
+    # the next eigenvalues nearest sigma, and [V1 V2], [Q1 Q2] form a partial
+    # generalized Schur form of (A, B)
+    rng = np.random.default_rng(seed)
+    n, k = 40, 3
+    A = rand_c(rng, n, n) + 3 * np.eye(n)
+    B = None if std else np.eye(n) + 0.3 * rand_c(rng, n, n)
+    sigma = complex(rng.normal(), rng.normal())
+    Bm = np.eye(n) if std else B
+    C = sp.csr_matrix(A - sigma * Bm)
+    T = O.make_preconditioner(C, "exact")
+    As, Bs = sp.csr_matrix(A), None if std else sp.csr_matrix(B)
+    r1 = O.gplhr(As, Bs, sigma, k, rand_c(rng, n, k), T, tol=1e-13, maxit=80)
+    assert r1.converged
+    V1, Q1 = r1.V, (r1.V if std else r1.Q)
+    r2 = O.gplhr_deflated(As, Bs, sigma, k, rand_c(rng, n, k), T, V1, Q1, tol=1e-12, maxit=80)
+    assert r2.converged
+    ref = nearest(sla.eigvals(A, Bm), sigma, 2 * k)
+    assert match_err(r1.lam[:k], ref[:k]) < 1e-9
+    assert match_err(r2.lam[:k], ref[k:]) < 1e-9
+    V = np.hstack([V1, r2.V])
+    Q = np.hstack([Q1, r2.V if std else r2.Q])
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(2 * k), atol=1e-10)
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(2 * k), atol=1e-10)
+    for M in ([A] if std else [A, B]):
+        R = Q.conj().T @ M @ V
+        assert np.abs(np.tril(R, -1)).max() < 1e-9 * np.abs(R).max()
+        assert np.linalg.norm(M @ V - Q @ R) < 1e-9 * np.linalg.norm(M @ V)
+
+
 def test_random_pencil_family_matches_zggev():
     A, B = problems.random_pencil(200, seed=0)
     As, Bs = A.to_scipy(), B.to_scipy()
