@@ -237,92 +237,15 @@ template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const i
 
 // ---------------------------------------------------------------------------
 // Gram matrices G = X^H diag(yscale) Y in FP64, deterministic
-// ---------------------------------------------------------------------------
-// Narrow X (bx <= 16): a lane owns one column q of Y and all bx columns of
-// X; the `lq` lanes of a group cover one row, so a wavefront reads 64/lq whole
-// rows of Y per instruction while the X entries of a row are broadcast (16-byte
-// loads).  Row slots are combined with wavefront shuffles and the four waves'
-// row groups in LDS, both in a fixed order.
-constexpr int GPB = 16;
-
-template <typename T>
-struct GramArgs {
-    int64_t n;
-    const T *X;
-    int ldx;
-    int bx;
-    const T *Y;
-    int ldy;
-    int by;
-    const T *yscale;
-    double2 *part;
-    int nblk;
-    int lq;     // lanes per row (power of two >= by)
-};
-
-template <typename T, bool PAIR>
-__global__ __launch_bounds__(256) void gram_kernel(GramArgs<T> a) {
-    __shared__ double2 red[GPB * 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lq = a.lq, rs = 64 / lq;
-    const int slot = lane / lq, q = lane - slot * lq;
-    const int pn = a.bx;
-    double2 acc[GPB];
-#pragma unroll
-    for (int i = 0; i < GPB; ++i) acc[i] = make_double2(0.0, 0.0);
-    if (q < a.by) {
-        const int64_t stride = (int64_t)a.nblk * 4 * rs;
-        for (int64_t r = ((int64_t)blockIdx.x * 4 + wave) * rs + slot; r < a.n; r += stride) {
-            double2 y = to_d(a.Y[r * a.ldy + q]);
-            if (a.yscale) y = cmul(to_d(a.yscale[r]), y);
-            double2 xv[GPB];
-            if constexpr (PAIR) {
-                const float4 *xr = reinterpret_cast<const float4 *>(a.X + r * a.ldx);
-#pragma unroll
-                for (int i = 0; i < GPB / 2; ++i) {
-                    const float4 t = (2 * i < pn) ? xr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    xv[2 * i] = make_double2(t.x, t.y);
-                    xv[2 * i + 1] = make_double2(t.z, t.w);
-                }
-            } else {
-                const T *xr = a.X + r * a.ldx;
-#pragma unroll
-                for (int i = 0; i < GPB; ++i) xv[i] = (i < pn) ? to_d(xr[i]) : make_double2(0.0, 0.0);
-            }
-#pragma unroll
-            for (int i = 0; i < GPB; ++i) cfma_cj(acc[i], xv[i], y);
-        }
-    }
-    for (int off = lq; off < 64; off <<= 1) {
-#pragma unroll
-        for (int i = 0; i < GPB; ++i) {
-            acc[i].x += __shfl_xor(acc[i].x, off);
-            acc[i].y += __shfl_xor(acc[i].y, off);
-        }
-    }
-    const bool owner = slot == 0 && q < a.by;
-    for (int g = 0; g < 4; ++g) {
-        if (owner && wave == g) {
-#pragma unroll
-            for (int i = 0; i < GPB; ++i) {
-                if (i < pn) {
-                    const int e = i + q * a.bx;
-                    red[e] = (g == 0) ? acc[i] : cadd(red[e], acc[i]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < a.bx * a.by; e += 256)
-        a.part[(int64_t)e * a.nblk + blockIdx.x] = red[e];
-}
-
-// Wide X (bx > 16): the complex product is the real GEMM
-// [Re X, Im X]^T [Re Y, Im Y] over the interleaved real views (n x 2bx and
-// n x 2by), computed with FP64 matrix instructions (16x16x4, FP64 accumulate;
-// complex64 inputs are widened, so every product is exact).  The waves of a
-// block split the N tiles (and the rows, when there are few N tiles); each
-// block owns a contiguous row range and writes a real partial Gram.
+// The complex product is the real GEMM [Re X, Im X]^T [Re Y, Im Y] over the
+// interleaved real views (n x 2bx and n x 2by), computed with FP64 matrix
+// instructions (16x16x4, FP64 accumulate; complex64 inputs are widened, so
+// every product is exact).  Output tiles (MT x NT of 16x16) are split among
+// the four waves of a block: G groups of N tiles, and ks = 4 / G row splits.
+// Each wave owns at most MTC x NTC tiles and streams its rows with the
+// operands of the next K step (4 rows) loaded while the current one is
+// multiplied.  Row splits are summed in LDS in a fixed order, and each block
+// writes a real partial Gram of its contiguous row range.
 template <typename T>
 struct GramMArgs {
     int64_t n;
@@ -336,129 +259,138 @@ struct GramMArgs {
     double *part;
     int nblk;
     int64_t rows_per_blk;
-    int MT, NT, G, ks;
+    int MT, NT, G, ks, NTg;
 };
 
 typedef double d4v __attribute__((ext_vector_type(4)));
-
 
 template <typename T> struct RealOf;
 template <> struct RealOf<double2> { using R = double; };
 template <> struct RealOf<float2> { using R = float; };
 
-constexpr int GM_U = 4;   // K steps (of 4 rows) whose operands are loaded ahead
+constexpr int GM_PF = 2;   // K steps in flight per wave
 
-template <typename T>
+template <typename T, int MTC, int NTC>
 __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     using R = typename RealOf<T>::R;
-    __shared__ double red[2][8][256];
+    __shared__ double red[2 * MTC * NTC * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = wave % a.G, h = wave / a.G;
     const bool active = h < a.ks;
     const int li = lane & 15, lk = lane >> 4;
     const int nbx = 2 * a.bx, nby = 2 * a.by;
-    d4v acc[8][2];
+    const int nt0 = g * a.NTg;
+    d4v acc[MTC][NTC];
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[mt][t] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < NTC; ++t) acc[mt][t] = d4v{0.0, 0.0, 0.0, 0.0};
     const int64_t rb = (int64_t)blockIdx.x * a.rows_per_blk;
     const int64_t re = min(a.n, rb + a.rows_per_blk);
-    const int64_t kstep = 4LL * a.ks;
-    if (active) {
-        for (int64_t r0 = rb + 4 * h; r0 < re; r0 += kstep * GM_U) {
-            double av[GM_U][8];   // widened once at load
-            double bv[GM_U][2];
+    const int64_t step = 4LL * a.ks;
+    const int64_t r = rb + 4 * h + lk;
+    const int64_t span = re - rb - 4 * h;
+    const int nst = span > 0 ? (int)((span + step - 1) / step) : 0;
+    double xa[GM_PF][MTC], yb[GM_PF][NTC];
+    // operands of the K step at `row` (zeros past the block's range)
+    auto load = [&](int p, int64_t row) {
+        const bool ok = row < re;
+        const int64_t rr = ok ? row : rb;
+        const R *xrow = reinterpret_cast<const R *>(a.X + rr * a.ldx);
 #pragma unroll
-            for (int u = 0; u < GM_U; ++u) {
-                const int64_t r = r0 + kstep * u + lk;
-                const bool ok = r < re;
-                const R *xrow = reinterpret_cast<const R *>(a.X + r * a.ldx);
+        for (int mt = 0; mt < MTC; ++mt) {
+            const int i = mt * 16 + li;
+            xa[p][mt] = (mt < a.MT && ok && i < nbx) ? (double)xrow[i] : 0.0;
+        }
+        const R *yrow = reinterpret_cast<const R *>(a.Y + rr * a.ldy);
+        double2 sc = make_double2(1.0, 0.0);
+        if (a.yscale && ok) sc = to_d(a.yscale[rr]);
 #pragma unroll
-                for (int mt = 0; mt < 8; ++mt) {
-                    const int i = mt * 16 + li;
-                    av[u][mt] = (mt < a.MT && ok && i < nbx) ? (double)xrow[i] : 0.0;
-                }
-                const R *yrow = reinterpret_cast<const R *>(a.Y + r * a.ldy);
-                double2 sc = make_double2(1.0, 0.0);
-                if (a.yscale && ok) sc = to_d(a.yscale[r]);
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int nt = g + t * a.G;
-                    const int j = nt * 16 + li;
-                    double v = 0.0;
-                    if (nt < a.NT && ok && j < nby) {
-                        if (a.yscale) {
-                            // (sc * y) for the complex entry that holds real j
-                            const double yr = yrow[j & ~1], yi = yrow[j | 1];
-                            v = (j & 1) ? (sc.x * yi + sc.y * yr) : (sc.x * yr - sc.y * yi);
-                        } else {
-                            v = yrow[j];
-                        }
-                    }
-                    bv[u][t] = v;
+        for (int t = 0; t < NTC; ++t) {
+            const int nt = nt0 + t;
+            const int j = nt * 16 + li;
+            double v = 0.0;
+            if (t < a.NTg && nt < a.NT && ok && j < nby) {
+                if (a.yscale) {
+                    // (sc * y) for the complex entry that holds real j
+                    const double yr = yrow[j & ~1], yi = yrow[j | 1];
+                    v = (j & 1) ? (sc.x * yi + sc.y * yr) : (sc.x * yr - sc.y * yi);
+                } else {
+                    v = yrow[j];
                 }
             }
+            yb[p][t] = v;
+        }
+    };
+    if (active) {
 #pragma unroll
-            for (int u = 0; u < GM_U; ++u)
+        for (int p = 0; p < GM_PF; ++p) load(p, r + (int64_t)p * step);
+        for (int j = 0; j < nst; j += GM_PF) {
 #pragma unroll
-                for (int mt = 0; mt < 8; ++mt) {
+            for (int p = 0; p < GM_PF; ++p) {
+#pragma unroll
+                for (int mt = 0; mt < MTC; ++mt) {
                     if (mt < a.MT) {
 #pragma unroll
-                        for (int t = 0; t < 2; ++t)
-                            if (g + t * a.G < a.NT)
+                        for (int t = 0; t < NTC; ++t)
+                            if (t < a.NTg && nt0 + t < a.NT)
                                 acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                    av[u][mt], bv[u][t], acc[mt][t], 0, 0, 0);
+                                    xa[p][mt], yb[p][t], acc[mt][t], 0, 0, 0);
                     }
                 }
+                load(p, r + (int64_t)(j + p + GM_PF) * step);
+            }
         }
     }
     // D(i, j) of a 16x16 tile (FP64 16x16x4 layout on gfx950): register v of
     // lane l holds i = 4 v + l / 16, j = l % 16
     auto store = [&](int mt, int nt, const d4v &d) {
-        const int j = nt * 16 + li;
+        const int jj = nt * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = mt * 16 + 4 * v + lk;
-            if (i < nbx && j < nby) a.part[(int64_t)(i + j * nbx) * a.nblk + blockIdx.x] = d[v];
+            if (i < nbx && jj < nby) a.part[(int64_t)(i + jj * nbx) * a.nblk + blockIdx.x] = d[v];
         }
     };
     if (a.ks == 1) {
         if (active) {
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt)
+            for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
-                    if (mt < a.MT && g + t * a.G < a.NT) store(mt, g + t * a.G, acc[mt][t]);
+                for (int t = 0; t < NTC; ++t)
+                    if (mt < a.MT && t < a.NTg && nt0 + t < a.NT) store(mt, nt0 + t, acc[mt][t]);
         }
         return;
     }
-    // ks > 1: one N tile per wave group; the row splits are summed in LDS in order h
+    // ks > 1 (then G <= 2): the row splits are summed in LDS in the order h
     for (int hh = 0; hh < a.ks; ++hh) {
         if (h == hh) {
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                if (mt < a.MT) {
+            for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        double &dst = red[g][mt][lane * 4 + v];
-                        dst = (hh == 0) ? acc[mt][0][v] : dst + acc[mt][0][v];
+                for (int t = 0; t < NTC; ++t) {
+                    if (mt < a.MT && t < a.NTg) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            double &dst = red[((g * MTC + mt) * NTC + t) * 256 + lane * 4 + v];
+                            dst = (hh == 0) ? acc[mt][t][v] : dst + acc[mt][t][v];
+                        }
                     }
                 }
-            }
         }
         __syncthreads();
     }
-    if (h == 0 && g < a.NT) {
+    if (h == 0) {
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-            if (mt < a.MT) {
-                d4v d;
+        for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) d[v] = red[g][mt][lane * 4 + v];
-                store(mt, g, d);
-            }
-        }
+            for (int t = 0; t < NTC; ++t)
+                if (mt < a.MT && t < a.NTg && nt0 + t < a.NT) {
+                    d4v d;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) d[v] = red[((g * MTC + mt) * NTC + t) * 256 + lane * 4 + v];
+                    store(mt, nt0 + t, d);
+                }
     }
 }
 
@@ -513,54 +445,53 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
+template <typename T, int MTC, int NTC>
+static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
+                                int ldo, int nblk_want) {
+    a.G = (a.NT + NTC - 1) / NTC;
+    if (a.G == 3) a.G = 4;
+    if (a.MT > MTC || a.G > 4) throw Error(-1, "gram: no tile layout for this shape");
+    a.NTg = (a.NT + a.G - 1) / a.G;
+    a.ks = 4 / a.G;
+    const int64_t step = 4LL * a.ks;
+    // at least a few K steps per wave, and the partials within the scratch
+    const int64_t per_blk = (int64_t)4 * a.bx * a.by;   // doubles
+    int64_t nblk = std::min<int64_t>(nblk_want, std::max<int64_t>(1, a.n / (step * 8)));
+    nblk = std::min<int64_t>(nblk, (int64_t)(2 * part_cap) / per_blk);
+    if (nblk < 1) throw Error(-1, "gram: partial buffer too small");
+    a.nblk = (int)nblk;
+    a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
+    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC>), dim3(a.nblk), dim3(256), 0, st, a);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(a.bx * a.by), dim3(256), 0, st, a.part,
+                       a.nblk, a.bx, out, ldo);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
                  int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo) {
     if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
     if (n <= 0) throw Error(-1, "gram: empty block");
-    if (bx <= GPB && by <= GPB) {
-        GramArgs<T> a{};
-        a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
-        a.yscale = yscale; a.part = part;
-        int lq = 1;
-        while (lq < by) lq <<= 1;
-        a.lq = lq;
-        const int64_t rows_per_pass = 4LL * (64 / lq);
-        const int64_t want = (n + rows_per_pass * 16 - 1) / (rows_per_pass * 16);
-        int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, want));
-        nblk = (int)std::min<size_t>(nblk, part_cap / ((size_t)bx * by));
-        a.nblk = nblk;
-        bool pair = false;
-        if constexpr (sizeof(T) == 8)
-            pair = (bx % 2 == 0) && (ldx % 2 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-        if (pair)
-            hipLaunchKernelGGL((gram_kernel<T, true>), dim3(nblk), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((gram_kernel<T, false>), dim3(nblk), dim3(256), 0, st, a);
-        GPLHR_HIP_CHECK(hipGetLastError());
-        launch_reduce_partials(st, part, nblk, bx, by, out, ldo);
-        return;
-    }
     GramMArgs<T> a{};
     a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
     a.yscale = yscale;
     a.part = reinterpret_cast<double *>(part);
     a.MT = (2 * bx + 15) / 16;
     a.NT = (2 * by + 15) / 16;
-    a.G = std::min(4, a.NT);
-    a.ks = 4 / a.G;
-    const size_t per_blk = (size_t)4 * bx * by;   // doubles
-    int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 511) / 512));
-    nblk = (int)std::min<size_t>(nblk, (2 * part_cap) / per_blk);
-    if (nblk < 1) throw Error(-1, "gram: partial buffer too small");
-    a.nblk = nblk;
-    const int64_t step = 4LL * a.ks;
-    a.rows_per_blk = ((n + nblk - 1) / nblk + step - 1) / step * step;
-    hipLaunchKernelGGL((gram_mfma_kernel<T>), dim3(nblk), dim3(256), 0, st, a);
-    GPLHR_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(bx * by), dim3(256), 0, st, a.part, nblk,
-                       bx, out, ldo);
-    GPLHR_HIP_CHECK(hipGetLastError());
+    // tile layout per wave by the number of M tiles (measured on n = 262144);
+    // few tiles: more blocks
+    const int nb = (a.MT * a.NT <= 9) ? 512 : 256;
+    if (a.MT <= 3)
+        gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT == 4)
+        gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT == 5)
+        gram_launch_variant<T, 5, 5>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT == 6)
+        gram_launch_variant<T, 6, 3>(st, a, part_cap, out, ldo, nb);
+    else
+        gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
 }
 template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
                                    const double2 *, int, int, const double2 *, double2 *, size_t,
