@@ -114,6 +114,117 @@ def named_iteration_times(G, torch, name, scale, its, precisions):
     return out
 
 
+def timed_solve(G, torch, p, precision, reps=2, **kw):
+    """Complete solves (create + iterate to 1e-10 + output) of a workload with
+    the given options: one untimed warm-up, then `reps` timed."""
+    A = G.DeviceCsr.from_host(p.A)
+    B = None if p.B is None else G.DeviceCsr.from_host(p.B)
+    V0 = torch.as_tensor(p.V0).to("cuda")
+    opts = dict(precond=p.precond, sweeps=p.sweeps or 3, omega=p.omega or 0.7, precision=precision,
+                V0=V0, tol=1e-10, max_iter=kw.pop("max_iter", 200))
+    if p.precond == "gmres":
+        opts.update(steps=p.steps, inner=p.inner)
+    opts.update(kw)
+
+    def once():
+        s = G.Solver(A, B, p.sigma, p.k, p.block, **opts)
+        st, _, res = s.iterate()
+        lam = s.lam()
+        stats = s.stats()
+        s.close()
+        return st, res, lam, stats
+
+    try:
+        once()
+    except G.GplhrError as e:
+        # a variant that breaks down (e.g. the LOBPCG-style P of Table 2)
+        del A, B, V0
+        return dict(converged=False, error=str(e)), None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st, res, lam, stats = once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del A, B, V0
+    return dict(s_per_solve=dt, iterations=stats["iterations"],
+                fp64_iterations=stats["fp64_iterations"], converged=(st == 0),
+                max_rel_resid=res), lam
+
+
+def deflation_5_plus_5(G, torch, p, reps=2):
+    """5 pairs, then 5 more on the deflated pair (two complete solves)."""
+    import numpy as np
+    A = G.DeviceCsr.from_host(p.A)
+    B = G.DeviceCsr.from_host(p.B)
+    V0 = torch.as_tensor(np.ascontiguousarray(p.V0[:, :5])).to("cuda")
+    opts = dict(precond=p.precond, V0=V0, tol=1e-10, max_iter=200)
+
+    def once():
+        s1 = G.Solver(A, B, p.sigma, 5, 5, **opts)
+        st1, _, _ = s1.iterate()
+        o1 = s1.schur()
+        s1.close()
+        s2 = G.Solver(A, B, p.sigma, 5, 5, deflate=(o1["V"], o1["Q"]), **opts)
+        st2, _, res = s2.iterate()
+        lam2 = s2.lam()
+        its = s2.stats()["iterations"]
+        s2.close()
+        return st1 == 0 and st2 == 0, res, np.concatenate([o1["lam"], lam2]), its
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ok, res, lam, its2 = once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del A, B, V0
+    return dict(s_per_solve=dt, converged=ok, max_rel_resid=res, second_run_iterations=its2), lam
+
+
+def eig_diff(a, b):
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(np.asarray(a)[:, None] - np.asarray(b)[None, :])
+    ri, ci = linear_sum_assignment(C)
+    return float(np.max(C[ri, ci] / np.abs(np.asarray(b)[ci])))
+
+
+def next_rows(G, torch, problems, lam_ref):
+    """The extensions of the method on the n = 262144 pencils, each a complete
+    solve to 1e-10; eigenvalues compared with the FP64 Schur-form solve."""
+    out = {}
+    d1 = problems.config("d1")
+    for key, prec, kw in [("locking", "fp64", dict(locking=True)),
+                          ("locking", "mixed", dict(locking=True)),
+                          ("eig_form", "fp64", dict(algorithm="eig")),
+                          ("eig_form", "mixed", dict(algorithm="eig")),
+                          ("p_lobpcg", "fp64", dict(p_mode="lobpcg", max_iter=60)),
+                          ("p_none", "fp64", dict(p_mode="none", max_iter=60)),
+                          ("eig_form_p_lobpcg", "fp64", dict(algorithm="eig", p_mode="lobpcg", max_iter=60))]:
+        r, lam = timed_solve(G, torch, d1, prec, **kw)
+        r["eig_rel_diff_vs_fp64_schur"] = eig_diff(lam, lam_ref) if r["converged"] else None
+        out.setdefault(key, {})[prec] = r
+        log(f"[bench] d1 {key} {prec}: {r}")
+    r, lam = deflation_5_plus_5(G, torch, d1)
+    r["eig_rel_diff_vs_fp64_schur"] = eig_diff(lam, lam_ref) if r["converged"] else None
+    out["deflation_5_plus_5"] = {"fp64": r}
+    log(f"[bench] d1 deflation 5+5: {r['s_per_solve']*1e3:.1f} ms, converged {r['converged']}")
+    d2 = problems.config("d2")
+    out["gmres_T_d2"] = {"workload": "diagonally dominant pencil with coupling 4, n=262144, k=b=10, "
+                                     "T = 2 block GMRES steps over 3 Jacobi sweeps"}
+    for prec in ("fp64", "mixed"):
+        r, _ = timed_solve(G, torch, d2, prec)
+        out["gmres_T_d2"][prec] = r
+        log(f"[bench] d2 GMRES T {prec}: {r['s_per_solve']*1e3:.1f} ms, {r['iterations']} its")
+    d2.precond = "jacobi"
+    r, _ = timed_solve(G, torch, d2, "fp64")
+    out["gmres_T_d2"]["jacobi3_only_fp64"] = r
+    log(f"[bench] d2 Jacobi-3 T fp64: {r['s_per_solve']*1e3:.1f} ms, {r['iterations']} its")
+    return out
+
+
 def cpu_baseline(p):
     from oracle import gplhr_oracle as O
     t0 = time.perf_counter()
@@ -132,6 +243,7 @@ def main():
     ap.add_argument("--scale", type=int, default=None, help="override n of the default workload")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the SpMM bandwidth measurement on the 160^3 operator (for profiling)")
+    ap.add_argument("--no-next", action="store_true", help="skip the extension rows")
     ap.add_argument("--named-only", action="store_true",
                     help="only the per-iteration timing of the named stencil workloads (for profiling)")
     args = ap.parse_args()
@@ -199,6 +311,10 @@ def main():
         f"c128 {sp128['gbs']:.0f} GB/s ({sp128['ms']:.3f} ms)")
     del c5A
 
+    nxt = None
+    if not args.no_next:
+        nxt = next_rows(G, torch, problems, out_d["lam"])
+
     named = {}
     if not args.no_named:
         named["c2_64cube_fp64_vs_c3_mixed"] = named_iteration_times(G, torch, "c2", None, 10, ["fp64", "mixed"])
@@ -241,13 +357,14 @@ def main():
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
-                     "kernel": "spmm_kernel<float2,2> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
+                     "kernel": "spmm_kernel<float2,4> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
                      "bytes_per_launch": sp64["bytes"], "ms_per_launch": sp64["ms"]},
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],
                  "c128_ms": sp128["ms"], "in_solve_ms_per_launch": spmm_ms_per,
                  "in_solve_bytes_per_launch": spmm_bytes_per},
         "solve_kernel_ms": {"spmm": stats_m["spmm_ms"], "gram": stats_m["gram_ms"],
                             "update": stats_m["update_ms"], "host_small_step": stats_m["small_host_ms"]},
+        "next_rows": nxt,
         "named_workloads": named,
         "cpu_baseline": cpu,
     }

@@ -26,7 +26,9 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
 ]
-HOST_ONLY = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", f"-I{CSRC}"]
+# -fcx-limited-range: textbook complex multiply/divide (no NaN/Inf recovery
+# calls); the small dense step never sees magnitudes near the overflow range
+HOST_ONLY = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", "-fcx-limited-range", f"-I{CSRC}"]
 
 
 def _compile(src: str, build_dir: Path) -> Path:
