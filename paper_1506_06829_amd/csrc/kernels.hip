@@ -243,9 +243,12 @@ template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const i
 // every product is exact).  Output tiles (MT x NT of 16x16) are split among
 // the four waves of a block: G groups of N tiles, and ks = 4 / G row splits.
 // Each wave owns at most MTC x NTC tiles and streams its rows with the
-// operands of the next K step (4 rows) loaded while the current one is
-// multiplied.  Row splits are summed in LDS in a fixed order, and each block
-// writes a real partial Gram of its contiguous row range.
+// operands of the next K step (4 rows) in flight while the current one is
+// multiplied: the loads go to raw registers from clamped, always valid
+// addresses, and widening, the B row scale and masking are applied only when
+// an operand is used, so nothing waits on a load before its turn.  Row splits
+// are summed in LDS in a fixed order, and each block writes a real partial
+// Gram of its contiguous row range.
 template <typename T>
 struct GramMArgs {
     int64_t n;
@@ -291,35 +294,30 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     const int64_t r = rb + 4 * h + lk;
     const int64_t span = re - rb - 4 * h;
     const int nst = span > 0 ? (int)((span + step - 1) / step) : 0;
-    double xa[GM_PF][MTC], yb[GM_PF][NTC];
-    // operands of the K step at `row` (zeros past the block's range)
+    R xa[GM_PF][MTC], yra[GM_PF][NTC], yia[GM_PF][NTC];
+    double scr[GM_PF], sci[GM_PF];
+    // raw operands of the K step at `row` (row 0, always valid, past the
+    // block's range; those operands are masked at use)
     auto load = [&](int p, int64_t row) {
-        const bool ok = row < re;
-        const int64_t rr = ok ? row : rb;
+        const int64_t rr = row < re ? row : 0;
         const R *xrow = reinterpret_cast<const R *>(a.X + rr * a.ldx);
 #pragma unroll
         for (int mt = 0; mt < MTC; ++mt) {
             const int i = mt * 16 + li;
-            xa[p][mt] = (mt < a.MT && ok && i < nbx) ? (double)xrow[i] : 0.0;
+            xa[p][mt] = xrow[i < nbx ? i : 0];
         }
-        const R *yrow = reinterpret_cast<const R *>(a.Y + rr * a.ldy);
-        double2 sc = make_double2(1.0, 0.0);
-        if (a.yscale && ok) sc = to_d(a.yscale[rr]);
+        if (a.yscale) {
+            const double2 sc = to_d(a.yscale[rr]);
+            scr[p] = sc.x;
+            sci[p] = sc.y;
+        }
 #pragma unroll
         for (int t = 0; t < NTC; ++t) {
-            const int nt = nt0 + t;
-            const int j = nt * 16 + li;
-            double v = 0.0;
-            if (t < a.NTg && nt < a.NT && ok && j < nby) {
-                if (a.yscale) {
-                    // (sc * y) for the complex entry that holds real j
-                    const double yr = yrow[j & ~1], yi = yrow[j | 1];
-                    v = (j & 1) ? (sc.x * yi + sc.y * yr) : (sc.x * yr - sc.y * yi);
-                } else {
-                    v = yrow[j];
-                }
-            }
-            yb[p][t] = v;
+            // the complex entry holding real column j
+            const int j = (nt0 + t) * 16 + li;
+            const T yc = a.Y[rr * a.ldy + ((j < nby ? j : 0) >> 1)];
+            yra[p][t] = yc.x;
+            yia[p][t] = yc.y;
         }
     };
     if (active) {
@@ -328,14 +326,34 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
         for (int j = 0; j < nst; j += GM_PF) {
 #pragma unroll
             for (int p = 0; p < GM_PF; ++p) {
+                const bool okp = (r + (int64_t)(j + p) * step) < re;
+                double xv[MTC], yv[NTC];
+#pragma unroll
+                for (int mt = 0; mt < MTC; ++mt) {
+                    const int i = mt * 16 + li;
+                    xv[mt] = (okp && i < nbx) ? (double)xa[p][mt] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < NTC; ++t) {
+                    const int jr = (nt0 + t) * 16 + li;
+                    double v = 0.0;
+                    if (okp && jr < nby) {
+                        const double yr = yra[p][t], yi = yia[p][t];
+                        if (a.yscale)   // (sc * y), the real (jr even) or imaginary part
+                            v = (jr & 1) ? (scr[p] * yi + sci[p] * yr) : (scr[p] * yr - sci[p] * yi);
+                        else
+                            v = (jr & 1) ? yi : yr;
+                    }
+                    yv[t] = v;
+                }
 #pragma unroll
                 for (int mt = 0; mt < MTC; ++mt) {
                     if (mt < a.MT) {
 #pragma unroll
                         for (int t = 0; t < NTC; ++t)
                             if (t < a.NTg && nt0 + t < a.NT)
-                                acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                    xa[p][mt], yb[p][t], acc[mt][t], 0, 0, 0);
+                                acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[mt], yv[t],
+                                                                                  acc[mt][t], 0, 0, 0);
                     }
                 }
                 load(p, r + (int64_t)(j + p + GM_PF) * step);
@@ -459,8 +477,9 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     int64_t nblk = std::min<int64_t>(nblk_want, std::max<int64_t>(1, a.n / (step * 8)));
     nblk = std::min<int64_t>(nblk, (int64_t)(2 * part_cap) / per_blk);
     if (nblk < 1) throw Error(-1, "gram: partial buffer too small");
-    a.nblk = (int)nblk;
     a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
+    // no block starts past the last row
+    a.nblk = (int)((a.n + a.rows_per_blk - 1) / a.rows_per_blk);
     hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(a.bx * a.by), dim3(256), 0, st, a.part,
@@ -482,7 +501,9 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
     // tile layout per wave by the number of M tiles (measured on n = 262144);
     // few tiles: more blocks
     const int nb = (a.MT * a.NT <= 9) ? 512 : 256;
-    if (a.MT <= 3)
+    if (a.MT <= 2 && a.NT <= 2)
+        gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT <= 3)
         gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4)
         gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
