@@ -130,7 +130,7 @@ struct Ctx {
               double2 *out);
     template <typename T>
     void update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1, int nterms,
-                const UpdTerm<T> *terms);
+                const UpdTerm<T> *terms, const T *add = nullptr, int ldadd = 0);
     template <typename T>
     void project(T *X, int ldx, int xcol, int wx, const T *Y, int ldy, int ycol, int wy,
                  T *mir1 = nullptr, const T *ymir1 = nullptr, T *mir2 = nullptr,

@@ -116,10 +116,11 @@ void Ctx::gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T
 
 template <typename T>
 void Ctx::update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1,
-                 int nterms, const UpdTerm<T> *terms) {
+                 int nterms, const UpdTerm<T> *terms, const T *add, int ldadd) {
     tbegin(T_UPDATE);
     launch_update<T>(st, n, out, ldo, wout, ocol, split, ocol2,
-                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms, ucoef);
+                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms, ucoef,
+                     add, ldadd);
     tend(T_UPDATE);
 }
 
@@ -569,11 +570,9 @@ void Ctx::iterate_once() {
         if (pos != offPs) {
             // the layout is narrower than the kept one: move P next to S_mc
             // (row-local, so overlapping column ranges are safe)
-            UpdTerm<T> t;
-            t.ld = ld; t.col = offPs; t.w = pa; t.M = eye; t.ldm = EYE_N;
-            t.in = Z;  update<T>(Z, ld, pa, pos, pa, 0, false, 1, &t);
-            t.in = CZ; update<T>(CZ, ld, pa, pos, pa, 0, false, 1, &t);
-            if (bz) { t.in = bz; update<T>(bz, ld, pa, pos, pa, 0, false, 1, &t); }
+            update<T>(Z, ld, pa, pos, pa, 0, false, 0, nullptr, Z + offPs, ld);
+            update<T>(CZ, ld, pa, pos, pa, 0, false, 0, nullptr, CZ + offPs, ld);
+            if (bz) update<T>(bz, ld, pa, pos, pa, 0, false, 0, nullptr, bz + offPs, ld);
         }
         for (int pass = 0; pass < 2; ++pass)
             project<T>(Z, ld, pos, pa, Z, ld, 0, pos, CZ, CZ, bz, bz);
@@ -583,11 +582,10 @@ void Ctx::iterate_once() {
     const int wq = s_cur - b;
     gram<T>(U, ld, b, CZ + b, ld, wq, nullptr, g0);
     {
-        UpdTerm<T> t[2];
-        t[0].in = CZ; t[0].ld = ld; t[0].col = b; t[0].w = wq; t[0].M = eye; t[0].ldm = EYE_N;
-        t[1].in = U; t[1].ld = ld; t[1].col = 0; t[1].w = b; t[1].M = g0; t[1].ldm = b;
-        t[1].alpha = make_double2(-1.0, 0.0);
-        update<T>(U, ld, wq, b, wq, 0, false, 2, t);
+        UpdTerm<T> t;
+        t.in = U; t.ld = ld; t.col = 0; t.w = b; t.M = g0; t.ldm = b;
+        t.alpha = make_double2(-1.0, 0.0);
+        update<T>(U, ld, wq, b, wq, 0, false, 1, &t, CZ + b, ld);
     }
     project<T>(U, ld, b, wq, U, ld, 0, b);
     cholqr<T>(U, ld, b, wq, 2, nullptr, nullptr);
@@ -1011,7 +1009,7 @@ void Ctx::eigvecs(double2 *X) {
 template void Ctx::iterate_once<double2>();
 template void Ctx::iterate_once<float2>();
 template void Ctx::update<double2>(double2 *, int, int, int, int, int, bool, int,
-                                   const UpdTerm<double2> *);
+                                   const UpdTerm<double2> *, const double2 *, int);
 
 }  // namespace gplhr
 namespace gplhr {

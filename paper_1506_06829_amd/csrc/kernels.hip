@@ -540,6 +540,8 @@ struct UpdArgs {
     UpdTerm<T> t[3];
     int wtot;
     const T *coef;   // wtot x wout, row-major, alpha folded
+    const T *add;    // added block (column c at add[c]) or null
+    int ldadd;
 };
 
 template <typename T>
@@ -635,6 +637,7 @@ __global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a, const T *__res
                         const int c = c0 + jl;
                         const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
                         T o = tile[rr * LDT + jl];
+                        if (a.add) o = cadd(o, a.add[(r0 + rr) * a.ldadd + c]);
                         T *dst = a.out + (r0 + rr) * a.ldo + oc;
                         if (use_beta) cfma(o, beta, *dst);
                         *dst = o;
@@ -648,9 +651,10 @@ __global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a, const T *__res
 
 template <typename T>
 void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
-                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef) {
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef,
+                   const T *add, int ldadd) {
     if (n <= 0) return;
-    if (nterms < 1 || nterms > 3 || wout < 1 || wout > 48) throw Error(-1, "update: bad shape");
+    if (nterms < (add ? 0 : 1) || nterms > 3 || wout < 1 || wout > 48) throw Error(-1, "update: bad shape");
     if (!coef) throw Error(-1, "update: no coefficient scratch");
     UpdArgs<T> a{};
     a.n = n; a.out = out; a.ldo = ldo; a.wout = wout; a.ocol = ocol; a.split = split;
@@ -660,11 +664,15 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
         a.t[t] = terms[t];
         wtot += terms[t].w;
     }
-    if (wtot < 1 || wtot > 128) throw Error(-1, "update: input too wide");
+    if (wtot > 128 || (wtot < 1 && !add)) throw Error(-1, "update: input too wide");
+    a.add = add;
+    a.ldadd = ldadd;
     a.wtot = wtot;
     a.coef = static_cast<const T *>(coef);
-    hipLaunchKernelGGL((coef_prep_kernel<T>), dim3(1), dim3(256), 0, st, a, static_cast<T *>(coef));
-    GPLHR_HIP_CHECK(hipGetLastError());
+    if (nterms > 0) {
+        hipLaunchKernelGGL((coef_prep_kernel<T>), dim3(1), dim3(256), 0, st, a, static_cast<T *>(coef));
+        GPLHR_HIP_CHECK(hipGetLastError());
+    }
     const int grid = (int)std::min<int64_t>((n + 63) / 64, 8192);
     constexpr int CH = (sizeof(T) == 16) ? 8 : 16;
     const int wo = wout <= 8 ? 8 : wout <= 16 ? 16 : wout <= 32 ? 32 : 48;
@@ -681,9 +689,11 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
-                                     double2, int, const UpdTerm<double2> *, void *);
+                                     double2, int, const UpdTerm<double2> *, void *,
+                                     const double2 *, int);
 template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, int, int, int,
-                                    double2, int, const UpdTerm<float2> *, void *);
+                                    double2, int, const UpdTerm<float2> *, void *,
+                                    const float2 *, int);
 
 // ---------------------------------------------------------------------------
 // Cholesky-QR factor (one workgroup, w <= 64)
