@@ -231,8 +231,7 @@ gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad
             GPLHR_HIP_CHECK(hipMemcpy(c.coefY, P.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice));
             gplhr::UpdTerm<double2> t;
             t.in = Y; t.ld = k; t.col = 0; t.w = k; t.M = c.coefY; t.ldm = k;
-            gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t,
-                                          c.ucoef);
+            gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
         }
         // y_e^H B x_e and ||B x_e||
         const double2 *bx = X;

@@ -119,7 +119,7 @@ void Ctx::update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool
                  int nterms, const UpdTerm<T> *terms, const T *add, int ldadd) {
     tbegin(T_UPDATE);
     launch_update<T>(st, n, out, ldo, wout, ocol, split, ocol2,
-                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms, ucoef,
+                     beta1 ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0), nterms, terms,
                      add, ldadd);
     tend(T_UPDATE);
 }
@@ -390,11 +390,12 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
         t.in = w.Z;
         update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
+        // C V and B V only: C P and B P are formed afresh after step 18
         t.in = w.CZ;
-        update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
+        update<T>(w.CZ, ld, b, 0, b, offP, false, 1, &t);
         if (bexp()) {
             t.in = w.BZ;
-            update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
+            update<T>(w.BZ, ld, b, 0, b, offP, false, 1, &t);
         }
         pw = nc - b;
         eig_orthonormalise<T>();
@@ -439,11 +440,12 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
     t.in = w.Z;
     update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
+    // C V and B V only: C P and B P are formed afresh after step 22
     t.in = w.CZ;
-    update<T>(w.CZ, ld, nc, 0, b, offP, false, 1, &t);
+    update<T>(w.CZ, ld, b, 0, b, offP, false, 1, &t);
     if (bexp()) {
         t.in = w.BZ;
-        update<T>(w.BZ, ld, nc, 0, b, offP, false, 1, &t);
+        update<T>(w.BZ, ld, b, 0, b, offP, false, 1, &t);
     }
     t.in = w.U; t.M = coefL;
     update<T>(w.U, ld, b, 0, b, 0, false, 1, &t);
@@ -564,19 +566,20 @@ void Ctx::iterate_once() {
     for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
         build(offW + (l - 1) * a, a, eig ? M1s : M1, eig ? M2s : M2, q + q * b, offW + l * a);
 
-    // step 22: P <- orth(P - [V W S][V W S]^H P), mirrored onto C P (and B P)
+    // step 22: P <- orth(P - [V W S][V W S]^H P), then C P (and B P)
     if (pa > 0) {
         T *bz = bexp() ? BZ : nullptr;
         if (pos != offPs) {
             // the layout is narrower than the kept one: move P next to S_mc
             // (row-local, so overlapping column ranges are safe)
             update<T>(Z, ld, pa, pos, pa, 0, false, 0, nullptr, Z + offPs, ld);
-            update<T>(CZ, ld, pa, pos, pa, 0, false, 0, nullptr, CZ + offPs, ld);
-            if (bz) update<T>(bz, ld, pa, pos, pa, 0, false, 0, nullptr, bz + offPs, ld);
         }
-        for (int pass = 0; pass < 2; ++pass)
-            project<T>(Z, ld, pos, pa, Z, ld, 0, pos, CZ, CZ, bz, bz);
-        cholqr<T>(Z, ld, pos, pa, 2, CZ, bz);
+        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, pos, pa, Z, ld, 0, pos);
+        cholqr<T>(Z, ld, pos, pa, 2, nullptr, nullptr);
+        // C P (and B P) by fresh sparse products: one SpMM moves fewer bytes
+        // than mirroring the four updates above onto C Z
+        cprod<T>(Z + pos, ld, CZ + pos, ld, pa);
+        bprod<T>(Z + pos, ld, BZ + pos, ld, pa);
     }
     // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])]
     const int wq = s_cur - b;
@@ -595,18 +598,13 @@ void Ctx::iterate_once() {
     if (sizeof(T) == sizeof(double2)) ++n_iter64;
 }
 
-// Exact C V, C P (and B V, B P) by fresh sparse products: removes the drift of
-// the mirrored products.
+// Exact C V (and B V) by fresh sparse products: removes the drift of the
+// mirrored products (C P and B P are always formed afresh after step 22).
 template <typename T>
 void Ctx::refresh_products() {
     Work<T> &w = W<T>();
-    const int ld = smax, offP = smax - b;
-    cprod<T>(w.Z, ld, w.CZ, ld, b);
-    bprod<T>(w.Z, ld, w.BZ, ld, b);
-    if (pw > 0) {
-        cprod<T>(w.Z + offP, ld, w.CZ + offP, ld, pw);
-        bprod<T>(w.Z + offP, ld, w.BZ + offP, ld, pw);
-    }
+    cprod<T>(w.Z, smax, w.CZ, smax, b);
+    bprod<T>(w.Z, smax, w.BZ, smax, b);
 }
 
 // Soft locking: q <- max(q, min(leading converged pairs, b - 1)) and the
@@ -995,12 +993,12 @@ void Ctx::eigvecs(double2 *X) {
         dalloc(&tmp, (size_t)n * b);
         launch_c64_to_c128(st, n, b, wf.Z, smax, tmp, b);
         t.in = tmp; t.ld = b;
-        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t, ucoef);
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
         dfree(tmp);
     } else {
         t.in = wd.Z; t.ld = smax;
-        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t, ucoef);
+        launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     }
 }

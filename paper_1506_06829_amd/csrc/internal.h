@@ -63,11 +63,9 @@ struct UpdTerm {
 // c < wout <= 48, with map(c) = ocol + c for c < split and ocol2 + (c - split)
 // otherwise; Add (ld ldadd, first column at the pointer) may be null, and
 // nterms may be 0 when it is not.  Row-local, so Out may alias any input.
-// `coef` is device scratch for the combined coefficients (at least 128 * 48
-// complex128 entries), reused by every call on the stream.
 template <typename T>
 void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
-                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef,
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms,
                    const T *add = nullptr, int ldadd = 0);
 
 // Cholesky-QR factor: given the w-by-w Gram G (column-major, Hermitian),

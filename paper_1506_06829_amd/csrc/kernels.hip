@@ -539,24 +539,10 @@ struct UpdArgs {
     int nterms;
     UpdTerm<T> t[3];
     int wtot;
-    const T *coef;   // wtot x wout, row-major, alpha folded
     const T *add;    // added block (column c at add[c]) or null
     int ldadd;
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void coef_prep_kernel(UpdArgs<T> a, T *coef) {
-    int base = 0;
-    for (int t = 0; t < a.nterms; ++t) {
-        const int w = a.t[t].w;
-        for (int e = threadIdx.x; e < w * a.wout; e += 256) {
-            const int j = e / a.wout, c = e - j * a.wout;
-            const double2 m = a.t[t].M[j + (int64_t)c * a.t[t].ldm];
-            coef[(base + j) * a.wout + c] = from_d<T>(cmul(a.t[t].alpha, m));
-        }
-        base += w;
-    }
-}
 
 // One wavefront per 64-row tile.  Input columns are staged through LDS in
 // chunks of CH with coalesced loads (consecutive lanes read consecutive
@@ -565,15 +551,33 @@ __global__ __launch_bounds__(256) void coef_prep_kernel(UpdArgs<T> a, T *coef) {
 // uniform across the wavefront (scalar loads).  Outputs leave through the
 // same LDS tile, again as coalesced row segments.
 template <typename T, int WO, int CH>
-__global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a, const T *__restrict__ coef) {
+__global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a) {
     extern __shared__ double2 sh_upd_raw[];
     constexpr int LDT = CH + 1;
     T *tile = reinterpret_cast<T *>(sh_upd_raw);          // 64 x LDT
     T *sM = tile + 64 * LDT;                               // wtot x WO (row-major)
     const int lane = threadIdx.x;
+    // combined coefficients alpha_t M_t, read straight from the terms (row j of
+    // the stacked inputs belongs to term 0, 1 or 2 by the widths)
+    const int w0 = a.t[0].w, w1 = a.nterms > 1 ? a.t[1].w : 0;
     for (int e = lane; e < a.wtot * WO; e += 64) {
         const int j = e / WO, c = e - j * WO;
-        sM[e] = (c < a.wout) ? coef[j * a.wout + c] : czero<T>();
+        T v = czero<T>();
+        if (c < a.wout) {
+            double2 m, al;
+            if (j < w0) {
+                m = a.t[0].M[j + (int64_t)c * a.t[0].ldm];
+                al = a.t[0].alpha;
+            } else if (j < w0 + w1) {
+                m = a.t[1].M[(j - w0) + (int64_t)c * a.t[1].ldm];
+                al = a.t[1].alpha;
+            } else {
+                m = a.t[2].M[(j - w0 - w1) + (int64_t)c * a.t[2].ldm];
+                al = a.t[2].alpha;
+            }
+            v = from_d<T>(cmul(al, m));
+        }
+        sM[e] = v;
     }
     const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
     const T beta = from_d<T>(a.beta);
@@ -651,11 +655,10 @@ __global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a, const T *__res
 
 template <typename T>
 void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int ocol, int split,
-                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, void *coef,
-                   const T *add, int ldadd) {
+                   int ocol2, double2 beta, int nterms, const UpdTerm<T> *terms, const T *add,
+                   int ldadd) {
     if (n <= 0) return;
     if (nterms < (add ? 0 : 1) || nterms > 3 || wout < 1 || wout > 48) throw Error(-1, "update: bad shape");
-    if (!coef) throw Error(-1, "update: no coefficient scratch");
     UpdArgs<T> a{};
     a.n = n; a.out = out; a.ldo = ldo; a.wout = wout; a.ocol = ocol; a.split = split;
     a.ocol2 = ocol2; a.beta = beta; a.nterms = nterms;
@@ -668,32 +671,27 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     a.add = add;
     a.ldadd = ldadd;
     a.wtot = wtot;
-    a.coef = static_cast<const T *>(coef);
-    if (nterms > 0) {
-        hipLaunchKernelGGL((coef_prep_kernel<T>), dim3(1), dim3(256), 0, st, a, static_cast<T *>(coef));
-        GPLHR_HIP_CHECK(hipGetLastError());
-    }
     const int grid = (int)std::min<int64_t>((n + 63) / 64, 8192);
     constexpr int CH = (sizeof(T) == 16) ? 8 : 16;
     const int wo = wout <= 8 ? 8 : wout <= 16 ? 16 : wout <= 32 ? 32 : 48;
     const size_t shmem = sizeof(T) * ((size_t)64 * (CH + 1) + (size_t)wtot * wo);
     if (shmem > 64 * 1024) throw Error(-1, "update: coefficient block exceeds LDS");
     if (wo == 8)
-        hipLaunchKernelGGL((update_kernel<T, 8, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+        hipLaunchKernelGGL((update_kernel<T, 8, CH>), dim3(grid), dim3(64), shmem, st, a);
     else if (wo == 16)
-        hipLaunchKernelGGL((update_kernel<T, 16, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+        hipLaunchKernelGGL((update_kernel<T, 16, CH>), dim3(grid), dim3(64), shmem, st, a);
     else if (wo == 32)
-        hipLaunchKernelGGL((update_kernel<T, 32, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+        hipLaunchKernelGGL((update_kernel<T, 32, CH>), dim3(grid), dim3(64), shmem, st, a);
     else
-        hipLaunchKernelGGL((update_kernel<T, 48, CH>), dim3(grid), dim3(64), shmem, st, a, a.coef);
+        hipLaunchKernelGGL((update_kernel<T, 48, CH>), dim3(grid), dim3(64), shmem, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
-                                     double2, int, const UpdTerm<double2> *, void *,
-                                     const double2 *, int);
+                                     double2, int, const UpdTerm<double2> *, const double2 *,
+                                     int);
 template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, int, int, int,
-                                    double2, int, const UpdTerm<float2> *, void *,
-                                    const float2 *, int);
+                                    double2, int, const UpdTerm<float2> *, const float2 *,
+                                    int);
 
 // ---------------------------------------------------------------------------
 // Cholesky-QR factor (one workgroup, w <= 64)
