@@ -15,6 +15,7 @@ import functools
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 import scipy.sparse as sp
 
 from oracle import gplhr_oracle as O
@@ -256,6 +257,36 @@ def test_converged_parity_full_size(device, precision, kw):
     s.close()
     assert st == 0 and res <= 1e-10
     assert match_err(lam[:p.k], _d1_reference()[:p.k]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_160cube_properties(device, precision):
+    # the largest workload (n = 4096000, k = b = 16, Jacobi-3) after three
+    # iterations, checked on the CPU from the GPU's outputs with properties that
+    # hold at any size: orthonormal V and Q, the eigenvalues are the
+    # Rayleigh-Ritz values of span(V), and the reported residuals are theirs
+    p = problems.config("c5")
+    s, _, _ = gpu_solver(p, precision=precision, tol=0.0, max_iter=3, switch_tol=0.0,
+                         stall_window=10**6)
+    s.iterate(3)
+    out = s.schur()
+    s.close()
+    V = out["V"].cpu().numpy()
+    Q = out["Q"].cpu().numpy()
+    k = p.k
+    orth_tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.abs(V.conj().T @ V - np.eye(k)).max() < orth_tol
+    assert np.abs(Q.conj().T @ Q - np.eye(k)).max() < orth_tol
+    A, B = p.A.to_scipy(), p.B.to_scipy()
+    AV, BV = A @ V, B @ V
+    lam, Zr = sla.eig(V.conj().T @ AV, V.conj().T @ BV)
+    order = np.argsort(np.abs(lam - p.sigma), kind="stable")
+    lam, Zr = lam[order], Zr[:, order] / np.linalg.norm(Zr[:, order], axis=0)
+    lam_tol = 1e-10 if precision == "fp64" else 1e-5
+    assert match_err(out["lam"], lam) < lam_tol
+    Ax, Bx = AV @ Zr, BV @ Zr
+    rho = np.linalg.norm(Ax - Bx * lam[None, :], axis=0) / np.linalg.norm(Ax, axis=0)
+    np.testing.assert_allclose(np.sort(out["rho"]), np.sort(rho), rtol=1e-6 if precision == "fp64" else 1e-2)
 
 
 def test_schur_outputs(device):
