@@ -122,7 +122,9 @@ struct SpmmArgs {
 
 constexpr int SPMM_BATCH = 8;
 
-template <typename T, int CPL>
+// MODE 0: Y = C X; MODE 1: the damped Jacobi sweep (compile-time, so the plain
+// product carries no epilogue registers)
+template <typename T, int CPL, int MODE>
 __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     int blk = blockIdx.x;
     if (a.per_xcd > 0) {
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 
     // epilogue operands first, so their latency overlaps the gather
     T xo[CPL], rh[CPL], w = czero<T>();
-    if (a.mode == 1) {
+    if constexpr (MODE == 1) {
         load_vec<T, CPL>(a.X + row * a.ldx + c0, xo);
         load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
         w = a.dw[row];
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
             for (int c = 0; c < CPL; ++c) cfma(acc[c], v[u], x[u][c]);
     }
     T out[CPL];
-    if (a.mode == 0) {
+    if constexpr (MODE == 0) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) out[c] = acc[c];
     } else {
@@ -219,12 +221,21 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
         grid = (nblocks + 7) / 8 * 8;
         a.per_xcd = grid / 8;
     }
-    if (cpl == 4)
-        hipLaunchKernelGGL((spmm_kernel<T, 4>), dim3(grid), dim3(256), 0, st, a);
-    else if (cpl == 2)
-        hipLaunchKernelGGL((spmm_kernel<T, 2>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((spmm_kernel<T, 1>), dim3(grid), dim3(256), 0, st, a);
+    if (mode == 0) {
+        if (cpl == 4)
+            hipLaunchKernelGGL((spmm_kernel<T, 4, 0>), dim3(grid), dim3(256), 0, st, a);
+        else if (cpl == 2)
+            hipLaunchKernelGGL((spmm_kernel<T, 2, 0>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((spmm_kernel<T, 1, 0>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        if (cpl == 4)
+            hipLaunchKernelGGL((spmm_kernel<T, 4, 1>), dim3(grid), dim3(256), 0, st, a);
+        else if (cpl == 2)
+            hipLaunchKernelGGL((spmm_kernel<T, 2, 1>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((spmm_kernel<T, 1, 1>), dim3(grid), dim3(256), 0, st, a);
+    }
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
