@@ -225,6 +225,25 @@ def next_rows(G, torch, problems, lam_ref):
     return out
 
 
+def large_time_to_solution(G, torch, problems, n=4096000):
+    """The same diagonally dominant family at the 160^3 size: complete solves
+    to 1e-10, mixed vs FP64 (one warm-up and one timed solve each)."""
+    p = problems.config("d1m", n)
+    out = {"workload": f"diagonally dominant generalized pencil n={p.n}, nnz={p.A.nnz}, "
+                       f"B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T=diag(A-sigma B)^-1"}
+    lams = {}
+    for prec in ("mixed", "fp64"):
+        r, lam = timed_solve(G, torch, p, prec, reps=1)
+        out[prec] = r
+        lams[prec] = lam
+        log(f"[bench] d1 n={p.n} {prec}: {r.get('s_per_solve', float('nan'))*1e3:.1f} ms, "
+            f"{r.get('iterations')} its, converged {r['converged']}")
+    if out["mixed"]["converged"] and out["fp64"]["converged"]:
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+        out["eig_rel_diff_mixed_vs_fp64"] = eig_diff(lams["mixed"], lams["fp64"])
+    return out
+
+
 def cpu_baseline(p):
     from oracle import gplhr_oracle as O
     t0 = time.perf_counter()
@@ -244,6 +263,8 @@ def main():
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the SpMM bandwidth measurement on the 160^3 operator (for profiling)")
     ap.add_argument("--no-next", action="store_true", help="skip the extension rows")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n = 4096000 mixed vs FP64 time-to-solution")
     ap.add_argument("--named-only", action="store_true",
                     help="only the per-iteration timing of the named stencil workloads (for profiling)")
     args = ap.parse_args()
@@ -315,6 +336,12 @@ def main():
     if not args.no_next:
         nxt = next_rows(G, torch, problems, out_d["lam"])
 
+    large = None
+    if not args.no_large:
+        log("[bench] building the n = 4096000 pencil for the large time-to-solution")
+        large = large_time_to_solution(G, torch, problems)
+        torch.cuda.empty_cache()
+
     named = {}
     if not args.no_named:
         named["c2_64cube_fp64_vs_c3_mixed"] = named_iteration_times(G, torch, "c2", None, 10, ["fp64", "mixed"])
@@ -365,6 +392,7 @@ def main():
         "solve_kernel_ms": {"spmm": stats_m["spmm_ms"], "gram": stats_m["gram_ms"],
                             "update": stats_m["update_ms"], "host_small_step": stats_m["small_host_ms"]},
         "next_rows": nxt,
+        "time_to_solution_4096000": large,
         "named_workloads": named,
         "cpu_baseline": cpu,
     }
