@@ -643,7 +643,8 @@ __global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a) {
                 const int cw = min(CH, a.wout - c0);
                 __syncthreads();
 #pragma unroll
-                for (int c = 0; c < CH; ++c) tile[lane * LDT + c] = acc[c0 + c];
+                for (int c = 0; c < CH; ++c)
+                    tile[lane * LDT + c] = (c0 + c < WO) ? acc[min(c0 + c, WO - 1)] : czero<T>();
                 __syncthreads();
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
@@ -684,17 +685,20 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     a.wtot = wtot;
     const int grid = (int)std::min<int64_t>((n + 63) / 64, 8192);
     constexpr int CH = (sizeof(T) == 16) ? 8 : 16;
-    const int wo = wout <= 8 ? 8 : wout <= 16 ? 16 : wout <= 32 ? 32 : 48;
+    // accumulator width: the smallest class >= wout (each lane computes WO outputs)
+    static const int classes[] = {4, 8, 10, 12, 16, 20, 24, 32, 40, 48};
+    int wo = 48;
+    for (int c : classes)
+        if (c >= wout) { wo = c; break; }
     const size_t shmem = sizeof(T) * ((size_t)64 * (CH + 1) + (size_t)wtot * wo);
     if (shmem > 64 * 1024) throw Error(-1, "update: coefficient block exceeds LDS");
-    if (wo == 8)
-        hipLaunchKernelGGL((update_kernel<T, 8, CH>), dim3(grid), dim3(64), shmem, st, a);
-    else if (wo == 16)
-        hipLaunchKernelGGL((update_kernel<T, 16, CH>), dim3(grid), dim3(64), shmem, st, a);
-    else if (wo == 32)
-        hipLaunchKernelGGL((update_kernel<T, 32, CH>), dim3(grid), dim3(64), shmem, st, a);
-    else
-        hipLaunchKernelGGL((update_kernel<T, 48, CH>), dim3(grid), dim3(64), shmem, st, a);
+    switch (wo) {
+#define GPLHR_UPD_CASE(W) \
+        case W: hipLaunchKernelGGL((update_kernel<T, W, CH>), dim3(grid), dim3(64), shmem, st, a); break;
+        GPLHR_UPD_CASE(4) GPLHR_UPD_CASE(8) GPLHR_UPD_CASE(10) GPLHR_UPD_CASE(12) GPLHR_UPD_CASE(16)
+        GPLHR_UPD_CASE(20) GPLHR_UPD_CASE(24) GPLHR_UPD_CASE(32) GPLHR_UPD_CASE(40) GPLHR_UPD_CASE(48)
+#undef GPLHR_UPD_CASE
+    }
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 template void launch_update<double2>(hipStream_t, int64_t, double2 *, int, int, int, int, int,
