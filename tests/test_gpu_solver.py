@@ -289,6 +289,43 @@ def test_full_size_160cube_properties(device, precision):
     np.testing.assert_allclose(np.sort(out["rho"]), np.sort(rho), rtol=1e-6 if precision == "fp64" else 1e-2)
 
 
+@pytest.mark.parametrize("k,block,locking", [(1, 1, False), (3, 6, True), (3, 6, False)])
+def test_converged_parity_block_shapes(device, k, block, locking):
+    # one wanted pair with a one-column block, and a block wider than k (the k
+    # leading pairs decide convergence), with and without soft locking
+    p = problems.config("d1", 3000)
+    p.k, p.block = k, block
+    p.V0 = problems.start_block(p.n, block)
+    s, _, _ = gpu_solver(p, max_iter=200, locking=locking)
+    st, nconv, res = s.iterate()
+    lam = s.lam()
+    s.close()
+    assert st == 0 and nconv == k and res <= 1e-10
+    ref = O.solve_problem(p, tol=1e-10, maxit=200, locking=locking)
+    assert ref.converged
+    assert match_err(lam[:k], ref.lam[:k]) < 1e-10
+
+
+def test_smallest_size_fills_the_space(device):
+    # n = (m + 3) b: the second iteration's trial subspace is the whole space,
+    # so its Rayleigh-Ritz values are exact eigenvalues (dense zggev)
+    rng = np.random.default_rng(31)
+    b, n = 4, 16
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 4 * np.eye(n)
+    Bm = np.eye(n) + 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    sigma = 0.4 + 0.2j
+    Ac = problems.csr_from_scipy(sp.csr_matrix(A))
+    Bc = problems.csr_from_scipy(sp.csr_matrix(Bm))
+    p = problems.Problem("tiny", Ac, Bc, sigma, b, b, "diag", tol=1e-12)
+    p.V0 = problems.start_block(n, b)
+    s, _, _ = gpu_solver(p, tol=0.0, max_iter=2)
+    s.iterate(2)
+    lam = s.lam()
+    s.close()
+    ref = nearest(sla.eigvals(A, Bm), sigma, b)
+    assert match_err(lam, ref) < 1e-10
+
+
 def test_schur_outputs(device):
     p = problems.config("d1", 3000)
     s, _, _ = gpu_solver(p, max_iter=100)
