@@ -384,7 +384,7 @@ def main():
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
-                     "kernel": "spmm_kernel<float2,4> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
+                     "kernel": "spmm_kernel<float2,4,0> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
                      "bytes_per_launch": sp64["bytes"], "ms_per_launch": sp64["ms"]},
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],
                  "c128_ms": sp128["ms"], "in_solve_ms_per_launch": spmm_ms_per,
