@@ -42,7 +42,6 @@ enum { T_SPMM = 0, T_GRAM = 1, T_UPDATE = 2 };
 struct Ctx {
     static constexpr size_t PART_CAP = (size_t)1024 * 64 * 64;   // complex128 scratch entries
     static constexpr int RESID_BLOCKS = 1024;
-    static constexpr int EYE_N = 64;
     static constexpr int REFRESH_EVERY = 20;
     static constexpr size_t GM_SLOT = 64 * 16;   // entries per block GMRES small factor
 
@@ -86,14 +85,12 @@ struct Ctx {
     Work<float2> wf;
 
     // small device buffers (FP64 complex)
-    double2 *part = nullptr, *g0 = nullptr, *g1 = nullptr, *rinv = nullptr, *eye = nullptr;
+    double2 *part = nullptr, *g0 = nullptr, *g1 = nullptr, *rinv = nullptr;
     double2 *coefY = nullptr, *coefL = nullptr, *M1 = nullptr, *M2 = nullptr;
     // coefficients of the S recursion: M_B, sigma M_B - M_A (Algorithm 2, the
     // same buffers as M1, M2) or Lambda_B, sigma Lambda_B - Lambda_A (Algorithm 3)
     double2 *M1s = nullptr, *M2s = nullptr;
     double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
-    double2 *xvec = nullptr;
-    double2 *ucoef = nullptr;   // combined update coefficients
     double2 *gmH = nullptr, *gmY = nullptr;   // block GMRES small factors (device)
     double2 *hgm = nullptr;                   // their pinned host staging
     int *dstatus = nullptr;

@@ -58,9 +58,9 @@ Ctx::~Ctx() {
     dfree(bd); dfree(bd32); dfree(dinv); dfree(dinv32); dfree(dw); dfree(dw32);
     for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
     for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
-    dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(eye); dfree(coefY); dfree(coefL);
+    dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(coefY); dfree(coefL);
     dfree(M1); dfree(M2); dfree(M1s); dfree(M2s); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
-    dfree(dstatus); dfree(xvec); dfree(ucoef); dfree(gmH); dfree(gmY);
+    dfree(dstatus); dfree(gmH); dfree(gmY);
     if (hpin) (void)hipHostFree(hpin);
     if (hgm) (void)hipHostFree(hgm);
 }
@@ -863,10 +863,9 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     }
     dalloc(&part, PART_CAP);
     dalloc(&g0, 64 * 64); dalloc(&g1, 64 * 64); dalloc(&rinv, 64 * 64);
-    dalloc(&eye, EYE_N * EYE_N); dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
+    dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
     dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&M1s, 64 * 64); dalloc(&M2s, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
     dalloc(&dZr, 64 * 64); dalloc(&dlam, 64); dalloc(&rnorm, 64); dalloc(&dstatus, 1);
-    dalloc(&ucoef, 128 * 64);
     if (gm) {
         dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT);
         dalloc(&gmY, 64 * 16);
@@ -874,11 +873,6 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
                                       hipHostMallocDefault));
     }
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
-    {
-        std::vector<double2> e(EYE_N * EYE_N, make_double2(0.0, 0.0));
-        for (int i = 0; i < EYE_N; ++i) e[i + i * EYE_N] = make_double2(1.0, 0.0);
-        GPLHR_HIP_CHECK(hipMemcpy(eye, e.data(), e.size() * sizeof(double2), hipMemcpyHostToDevice));
-    }
     GPLHR_HIP_CHECK(hipHostMalloc((void **)&hpin, sizeof(double2) * 4 * 64 * 64 + 4096, hipHostMallocDefault));
 
     // V0 -> Z(:, 0:b), then steps 1-4
