@@ -291,6 +291,22 @@ gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr,
 gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
                         const void *Y, int ldy, int by, void *G, void *hip_stream);
 
+/* Y(:, 0:wy) = beta Y(:, 0:wy) + X(:, 0:wx) M, the row-local block update
+ * behind every basis change of Algorithm 2: the new V, P and Q from the trial
+ * and test bases and the ordered Schur vectors (Section 3.5), the projections
+ * (I - QQ*) and (I - VV*) (Sections 3.3 and 3.4) and the Cholesky-QR
+ * normalisations.  X (n-by-wx, ldx >= wx) and Y (n-by-wy, ldy >= wy) are
+ * row-major device blocks of dtype 0 (complex128) or 1 (complex64, FP32
+ * accumulation); M is a device complex128 wx-by-wy array, column-major with
+ * leading dimension ldm >= wx.  Every row of X is read before the same row
+ * of Y is written, so Y may be X itself (same pointer and ld).
+ * 1 <= wx <= 128, 1 <= wy <= 48; returns ARG otherwise, and also when the
+ * coefficients (about wx * wy complex values, padded) exceed the 64 KiB of
+ * LDS the kernels stage them in. */
+gplhr_status gplhr_block_update(int dtype, int64_t n, const void *X, int ldx, int wx,
+                                const void *M, int ldm, void *Y, int ldy, int wy,
+                                double beta_re, double beta_im, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -364,4 +364,30 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
     });
 }
 
+gplhr_status gplhr_block_update(int dtype, int64_t n, const void *X, int ldx, int wx,
+                                const void *M, int ldm, void *Y, int ldy, int wy,
+                                double beta_re, double beta_im, void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 1 || wx < 1 || wx > 128 || wy < 1 || wy > 48 || ldx < wx || ldy < wy ||
+            ldm < wx || (dtype != 0 && dtype != 1) || !X || !M || !Y)
+            throw gplhr::Error(-1, "gplhr_block_update: bad arguments");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const double2 beta = make_double2(beta_re, beta_im);
+        if (dtype == 0) {
+            gplhr::UpdTerm<double2> t;
+            t.in = static_cast<const double2 *>(X); t.ld = ldx; t.w = wx;
+            t.M = static_cast<const double2 *>(M); t.ldm = ldm;
+            gplhr::launch_update<double2>(st, n, static_cast<double2 *>(Y), ldy, wy, 0, wy, 0,
+                                          beta, 1, &t);
+        } else {
+            gplhr::UpdTerm<float2> t;
+            t.in = static_cast<const float2 *>(X); t.ld = ldx; t.w = wx;
+            t.M = static_cast<const double2 *>(M); t.ldm = ldm;
+            gplhr::launch_update<float2>(st, n, static_cast<float2 *>(Y), ldy, wy, 0, wy, 0, beta,
+                                         1, &t);
+        }
+        return 0;
+    });
+}
+
 }  // extern "C"

@@ -68,7 +68,7 @@ class _Stats(ctypes.Structure):
 EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
-           "gplhr_last_error", "gplhr_spmm", "gplhr_gram"]
+           "gplhr_last_error", "gplhr_spmm", "gplhr_gram", "gplhr_block_update"]
 
 
 def lib():
@@ -106,6 +106,9 @@ def lib():
     L.gplhr_spmm.restype = i32
     L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
     L.gplhr_gram.restype = i32
+    L.gplhr_block_update.argtypes = [i32, i64, vp, i32, i32, vp, i32, vp, i32, i32,
+                                     ctypes.c_double, ctypes.c_double, vp]
+    L.gplhr_block_update.restype = i32
     _lib = L
     return L
 
@@ -287,6 +290,26 @@ def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
         Y = torch.empty((A.n, b), dtype=X.dtype, device=X.device)
     _check(lib().gplhr_spmm(dtype, A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
                             X.stride(0), _ptr(Y), Y.stride(0), b, _stream_ptr()))
+    return Y
+
+
+def block_update(X: torch.Tensor, M: torch.Tensor, Y: Optional[torch.Tensor] = None,
+                 beta: complex = 0.0) -> torch.Tensor:
+    """Y = beta Y + X M with the library's row-local update (X, Y complex128 or
+    complex64 row-major with unit column stride, M complex128 wx-by-wy); Y may
+    be X itself."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+    wx, wy = X.shape[1], M.shape[1]
+    assert X.dim() == 2 and X.stride(1) == 1 and M.shape[0] == wx
+    assert M.dtype == torch.complex128
+    Mc = M.t().contiguous()                       # column-major wx x wy
+    if Y is None:
+        Y = torch.zeros((X.shape[0], wy), dtype=X.dtype, device=X.device)
+    assert Y.dtype == X.dtype and Y.stride(1) == 1 and Y.shape == (X.shape[0], wy)
+    beta = complex(beta)
+    _check(lib().gplhr_block_update(dtype, X.shape[0], _ptr(X), X.stride(0), wx, _ptr(Mc), wx,
+                                    _ptr(Y), Y.stride(0), wy, beta.real, beta.imag,
+                                    _stream_ptr()))
     return Y
 
 

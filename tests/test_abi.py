@@ -17,7 +17,8 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     syms = declared_symbols()
     for s in ["gplhr_create", "gplhr_iterate", "gplhr_get_schur", "gplhr_eig_backward",
-              "gplhr_destroy", "gplhr_last_error", "gplhr_spmm", "gplhr_gram"]:
+              "gplhr_destroy", "gplhr_last_error", "gplhr_spmm", "gplhr_gram",
+              "gplhr_block_update"]:
         assert s in syms
 
 
@@ -51,6 +52,9 @@ def test_argument_errors_without_device_work():
     assert L.gplhr_spmm(0, 10, None, None, None, None, 4, None, 4, 0, None) == -1
     assert L.gplhr_spmm(0, 10, None, None, None, None, 2, None, 4, 4, None) == -1
     assert L.gplhr_gram(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
+    for wx, wy in [(0, 4), (129, 4), (4, 0), (4, 49)]:
+        assert L.gplhr_block_update(0, 10, None, 200, wx, None, 200, None, 200, wy,
+                                    ctypes.c_double(0.0), ctypes.c_double(0.0), None) == -1
     assert L.gplhr_iterate(None, 1, None, None) == -1
 
 

@@ -1,5 +1,6 @@
 """Parity of the single HIP kernels (through the C ABI) with their definitions
-on the CPU: sparse matrix times block, and the FP64-accumulated Gram matrix."""
+on the CPU: sparse matrix times block, the FP64-accumulated Gram matrix and
+the row-local block update."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -80,3 +81,62 @@ def test_gram_matches_definition(device, bx, by, dtype, n):
     scale = np.abs(X).T @ np.abs(Y)
     assert np.max(np.abs(Gm - ref) / scale) < 1e-13     # FP64 accumulation in both dtypes
     assert np.array_equal(Gm, G.gram(Xd, Yd).cpu().numpy())
+
+
+@pytest.mark.parametrize("wx,wy", [(1, 1), (7, 5), (10, 10), (16, 16), (40, 20), (30, 10), (10, 30),
+                                   (64, 32), (64, 16), (48, 48), (16, 48), (33, 40), (128, 8)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("beta", [0.0, 1.0, 0.5 - 0.25j])
+def test_block_update_matches_definition(device, wx, wy, dtype, beta):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(wx * 64 + wy)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    for n in (1, 17, 1000, 100003):
+        X = _block(rng, n, wx, ld=wx + 3)
+        Y0 = _block(rng, n, wy, ld=wy + 2)
+        M = rng.standard_normal((wx, wy)) + 1j * rng.standard_normal((wx, wy))
+        if dtype == "c64":
+            X = X.astype(np.complex64).astype(np.complex128)
+            Y0 = Y0.astype(np.complex64).astype(np.complex128)
+        Xd = torch.as_tensor(X).to(device, tdt)[:, :wx]          # strided blocks
+        Yfull = torch.as_tensor(Y0).to(device, tdt)
+        Md = torch.as_tensor(M).to(device)
+        out = G.block_update(Xd, Md, Yfull[:, :wy], beta=beta).cpu().numpy()
+        ref = beta * Y0[:, :wy] + X[:, :wx] @ M
+        scale = abs(beta) * np.abs(Y0[:, :wy]) + np.abs(X[:, :wx]) @ np.abs(M)
+        tol = 1e-14 if dtype == "c128" else 3e-6
+        assert np.max(np.abs(out - ref) / scale) < tol, (n, wx, wy)
+        # the columns past wy are left alone
+        rest = Yfull[:, wy:].cpu().numpy()
+        assert np.array_equal(rest, Y0[:, wy:].astype(rest.dtype))
+
+
+@pytest.mark.parametrize("w", [10, 16, 48])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_update_in_place(device, w, dtype):
+    # Y = X itself (the Cholesky-QR normalisation W <- W R^-1 is done this way)
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(w)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    n = 100003
+    X = _block(rng, n, w)
+    if dtype == "c64":
+        X = X.astype(np.complex64).astype(np.complex128)
+    M = np.triu(rng.standard_normal((w, w)) + 1j * rng.standard_normal((w, w))) + 3 * np.eye(w)
+    Xd = torch.as_tensor(X).to(device, tdt)
+    G.block_update(Xd, torch.as_tensor(M).to(device), Xd)
+    ref = X @ M
+    scale = np.abs(X) @ np.abs(M)
+    tol = 1e-14 if dtype == "c128" else 3e-6
+    assert np.max(np.abs(Xd.cpu().numpy() - ref) / scale) < tol
+
+
+def test_block_update_rejects_oversized_coefficients(device):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    X = torch.zeros((64, 128), dtype=torch.complex128, device=device)
+    M = torch.zeros((128, 48), dtype=torch.complex128, device=device)
+    with pytest.raises(Exception, match="LDS"):
+        G.block_update(X, M)
