@@ -29,10 +29,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # HBM-side bytes per launch of the complex64 SpMM on the 160^3 operator with a
-# 16-wide block: rocprofv3 FETCH_SIZE (x2.000) + WRITE_SIZE (x1.000), the
-# scales being what the same counters read for a 256 MiB device copy.  Valid
-# for the current spmm_kernel; re-measure after any change to it.
-SPMM_C64_160_B16_TRAFFIC = 1.964e9 + 0.524e9
+# 16-wide block in the solver's plane-slab row schedule: rocprofv3 FETCH_SIZE
+# (x2.000) + WRITE_SIZE (x1.000), the scales being what the same counters read
+# for a 256 MiB device copy.  Valid for the current spmm_kernel and schedule;
+# re-measure after any change to either.
+SPMM_C64_160_B16_TRAFFIC = 929202176 + 524288000
 METRIC = "time to k eigenpairs @1e-10 rel. residual, mixed vs FP64; SpMM HBM GB/s"
 
 
@@ -64,20 +65,23 @@ def time_solves(G, torch, A, B, p, precision, V0, steps, warmup, timing):
     return dt, runs
 
 
-def spmm_hbm(G, torch, csr, b, dtype, reps=20):
-    """Event-timed CSR SpMM (library kernel) on torch's current stream."""
+def spmm_hbm(G, torch, csr, b, dtype, reps=20, plane=None):
+    """Event-timed CSR SpMM (library kernel) on torch's current stream, in the
+    row schedule the solver uses for this pattern (plane=None) or a given one."""
     A = G.DeviceCsr.from_host(csr)
+    if plane is None:
+        plane = G.csr_plane(A)
     tdt = torch.complex64 if dtype == "c64" else torch.complex128
     val = A.val.to(tdt)
     X = torch.randn(csr.n, b, dtype=tdt, device="cuda")
     Y = torch.empty_like(X)
     for _ in range(3):
-        G.spmm(A, X, Y, val=val)
+        G.spmm(A, X, Y, val=val, plane=plane)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
-        G.spmm(A, X, Y, val=val)
+        G.spmm(A, X, Y, val=val, plane=plane)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -85,7 +89,7 @@ def spmm_hbm(G, torch, csr, b, dtype, reps=20):
     nbytes = csr.nnz * (e + 4) + 4 * (csr.n + 1) + 2 * csr.n * b * e
     del A, val, X, Y
     torch.cuda.empty_cache()
-    return dict(ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6)
+    return dict(ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6, plane=plane)
 
 
 def named_iteration_times(G, torch, name, scale, its, precisions):
@@ -280,7 +284,10 @@ def main():
 
     if args.spmm_only:
         c5A = problems.convection_diffusion(160, (20.0, 10.0, 5.0))
+        # the solver's schedule (plane = 160^2 rows) for both precisions, then
+        # the natural row order for comparison (dispatches in this order)
         res = {dt: spmm_hbm(G, torch, c5A, 16, dt) for dt in ("c64", "c128")}
+        res["c64_natural_order"] = spmm_hbm(G, torch, c5A, 16, "c64", plane=0)
         # a plain device copy of known size, for scaling hardware byte counters
         x = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device="cuda")
         y = torch.empty_like(x)
@@ -384,7 +391,8 @@ def main():
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
-                     "kernel": "spmm_kernel<float2,4,0> (CSR x 16-wide complex64 block, 160^3 upwind operator)",
+                     "kernel": "spmm_kernel<float2,4,0> (CSR x 16-wide complex64 block, 160^3 upwind operator, "
+                               f"plane-slab row schedule, plane {sp64['plane']})",
                      "bytes_per_launch": sp64["bytes"], "ms_per_launch": sp64["ms"]},
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],
                  "c128_ms": sp128["ms"], "in_solve_ms_per_launch": spmm_ms_per,

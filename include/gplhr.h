@@ -278,11 +278,22 @@ const char *gplhr_last_error(gplhr_t h);
  * the remarks that follow Algorithm 2).  All pointers are device pointers.
  * val, X, Y are complex128 (dtype 0) or complex64 (dtype 1, FP32
  * accumulation).  X has ldx >= b, Y has ldy >= b, Y must not overlap X.
- * col_idx and val may be NULL only when every row is empty.
- * Returns ARG for b < 1 or b > 64 or bad leading dimensions. */
+ * col_idx and val may be NULL only when every row is empty.  plane = 0 runs
+ * the rows in natural order; plane > 0 (a divisor of n and a multiple of 8,
+ * e.g. from gplhr_csr_plane) runs them plane by plane, each XCD of the GPU on
+ * its own slab of every plane, for matrices whose couplings stay within
+ * +-plane rows; the result is the same either way.
+ * Returns ARG for b < 1 or b > 64, bad leading dimensions or a bad plane. */
 gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr,
                         const int32_t *col_idx, const void *val, const void *X,
-                        int ldx, void *Y, int ldy, int b, void *hip_stream);
+                        int ldx, void *Y, int ldy, int b, int plane, void *hip_stream);
+
+/* The plane the solver uses for a CSR pattern (device row_ptr / col_idx with
+ * sorted columns): its bandwidth max |j - i| when that splits n into at least
+ * four planes of at least 512 rows and is a multiple of 8, else 0.  Reads the
+ * pattern once on hip_stream and waits for it. */
+gplhr_status gplhr_csr_plane(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             int *plane, void *hip_stream);
 
 /* G = X^H Y in complex128 (FP64 accumulation, deterministic order) for
  * row-major X (n-by-bx, ldx) and Y (n-by-by, ldy) of dtype 0 (complex128) or

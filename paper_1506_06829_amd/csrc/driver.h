@@ -56,7 +56,8 @@ struct Ctx {
     int k = 0, b = 0, m = 1, smax = 0, m_cur = 1, q = 0, pw = 0;
     cd sigma;
     BKind bk = B_IDENT;
-    bool mixed = false, xcd_remap = false;
+    bool mixed = false;
+    int c_plane = 0, b_plane = 0;   // SpMM row schedules of C and B
     bool eig = false;   // GPLHR-EIG (Algorithm 3) instead of the Schur form
     int defl_k = 0;     // columns of the deflation bases (0: no deflation)
     // B Z kept as an explicit block (general sparse B, or any B != I under

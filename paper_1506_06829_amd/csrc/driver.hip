@@ -169,7 +169,7 @@ template <typename T>
 void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int wc, int mode, const T *Rhs, int ldr) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, xcd_remap);
+    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, c_plane);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
@@ -180,7 +180,7 @@ template <typename T>
 void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy, int wc) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, wc, 0, nullptr, 0, nullptr, xcd_remap);
+    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, wc, 0, nullptr, 0, nullptr, b_plane);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * wc * sizeof(T);
@@ -798,6 +798,8 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     // a1: C = A - sigma B on the union pattern, its diagonal, the preconditioner
     c_nnz = build_shifted(st, n, a_rp, a_ci, a_val, bk == B_IDENT ? 0 : 1, b_rp, b_ci, b_val,
                           to_d2(sigma), &c_rp, &c_ci, &c_val);
+    c_plane = spmm_plane(st, n, c_rp, c_ci);
+    if (bk == B_SPARSE) b_plane = spmm_plane(st, n, b_rp, b_ci);
     if (ik != GPLHR_PRECOND_NONE) {
         double2 *dg = nullptr;
         dalloc(&dg, n);

@@ -118,6 +118,9 @@ struct SpmmArgs {
     int rpw;        // rows per wavefront
     int nblocks;    // blocks that carry rows
     int per_xcd;    // >0: XCD-contiguous block remap
+    int sp;         // >0: plane-slab row schedule with planes of sp rows
+    int ss;         // slab: sp / 8 rows of each plane
+    int sperx;      // rows per XCD: n / 8
 };
 
 constexpr int SPMM_BATCH = 8;
@@ -135,9 +138,15 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     const int wave = threadIdx.x >> 6;
     const int rw = lane / a.lpr;
     const int cl = lane - rw * a.lpr;
-    const int64_t row = ((int64_t)blk * 4 + wave) * a.rpw + rw;
+    const int64_t pos = ((int64_t)blk * 4 + wave) * a.rpw + rw;
     const int c0 = cl * CPL;
-    if (rw >= a.rpw || row >= a.n || c0 >= a.b) return;
+    if (rw >= a.rpw || pos >= a.n || c0 >= a.b) return;
+    int64_t row = pos;
+    if (a.sp > 0) {
+        // XCD x takes slab x of every plane, planes in order (n < 2^31)
+        const int p = (int)pos, x = p / a.sperx, r = p - x * a.sperx, z = r / a.ss;
+        row = (int64_t)z * a.sp + (int64_t)x * a.ss + (r - z * a.ss);
+    }
 
     // epilogue operands first, so their latency overlaps the gather
     T xo[CPL], rh[CPL], w = czero<T>();
@@ -191,12 +200,23 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     store_vec<T, CPL>(a.Y + row * a.ldy + c0, out);
 }
 
+// Row schedule.  Without a plane, rows run in natural order and blocks are
+// dealt to the XCDs round robin, so the block rows a row gathers (its
+// neighbours one plane away, for a PDE operator in natural ordering) are
+// fetched into several XCDs' L2.  With a plane of P rows (all couplings
+// within +-P rows, n a multiple of P, P a multiple of 8), blocks are remapped
+// so that XCD x runs slab x (rows x P/8 ... (x+1) P/8 - 1) of every plane,
+// plane after plane: the three planes of one slab that a block touches fit
+// in that XCD's L2, and every block row is fetched about once (160^3 operator,
+// 16 complex64 columns: 1.96 -> 0.93 GB read per product).
 template <typename T>
 void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, const T *val,
                  const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
-                 const T *dw, bool xcd_remap) {
+                 const T *dw, int plane) {
     if (n <= 0) return;
-    SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0};
+    if (plane < 0 || (plane > 0 && (n % plane != 0 || plane % 8 != 0)))
+        throw Error(-1, "spmm: the plane must divide n and be a multiple of 8");
+    SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0, 0, 0, 0};
     // lanes move 32 bytes of the block row: 4 complex64 or 2 complex128 values
     const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
                             (mode == 1 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
@@ -217,9 +237,12 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
     const int nblocks = ceil_div_i(n, rows_per_block);
     a.nblocks = nblocks;
     int grid = nblocks;
-    if (xcd_remap && nblocks >= 64) {
+    if (plane > 0) {
         grid = (nblocks + 7) / 8 * 8;
         a.per_xcd = grid / 8;
+        a.sp = plane;
+        a.ss = plane / 8;
+        a.sperx = (int)(n / 8);
     }
     if (mode == 0) {
         if (cpl == 4)
@@ -241,10 +264,50 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
 
 template void launch_spmm<double2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
                                    const double2 *, const double2 *, int, double2 *, int, int,
-                                   int, const double2 *, int, const double2 *, bool);
+                                   int, const double2 *, int, const double2 *, int);
 template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
                                   const float2 *, const float2 *, int, float2 *, int, int, int,
-                                  const float2 *, int, const float2 *, bool);
+                                  const float2 *, int, const float2 *, int);
+
+// Largest |j - i| over the stored entries (columns sorted within each row:
+// the first and the last entry of a row bound it).
+__global__ void bandwidth_kernel(int64_t n, const int32_t *rp, const int32_t *ci,
+                                 unsigned long long *out) {
+    __shared__ unsigned long long sh[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long d = 0;
+    if (i < n) {
+        const int lo = rp[i], hi = rp[i + 1];
+        if (hi > lo) {
+            const int64_t left = i - ci[lo], right = (int64_t)ci[hi - 1] - i;
+            d = (unsigned long long)max(max(left, right), (int64_t)0);
+        }
+    }
+    sh[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sh[0] > 0) atomicMax(out, sh[0]);
+}
+
+int spmm_plane(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci) {
+    if (n < 4096) return 0;
+    unsigned long long *bw = nullptr;
+    GPLHR_HIP_CHECK(hipMallocAsync((void **)&bw, sizeof(unsigned long long), st));
+    GPLHR_HIP_CHECK(hipMemsetAsync(bw, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(bandwidth_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, rp, ci, bw);
+    GPLHR_HIP_CHECK(hipGetLastError());
+    unsigned long long h = 0;
+    GPLHR_HIP_CHECK(hipMemcpyAsync(&h, bw, sizeof(h), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    GPLHR_HIP_CHECK(hipFreeAsync(bw, st));
+    // planes of at least 512 rows, at least four of them
+    const int64_t p = (int64_t)h;
+    if (p >= 512 && p % 8 == 0 && n % p == 0 && n / p >= 4) return (int)p;
+    return 0;
+}
 
 // ---------------------------------------------------------------------------
 // Gram matrices G = X^H diag(yscale) Y in FP64, deterministic

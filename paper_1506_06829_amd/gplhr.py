@@ -68,7 +68,8 @@ class _Stats(ctypes.Structure):
 EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
-           "gplhr_last_error", "gplhr_spmm", "gplhr_gram", "gplhr_block_update"]
+           "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram",
+           "gplhr_block_update"]
 
 
 def lib():
@@ -102,8 +103,10 @@ def lib():
     L.gplhr_destroy.restype = None
     L.gplhr_last_error.argtypes = [vp]
     L.gplhr_last_error.restype = ctypes.c_char_p
-    L.gplhr_spmm.argtypes = [i32, i64, vp, vp, vp, vp, i32, vp, i32, i32, vp]
+    L.gplhr_spmm.argtypes = [i32, i64, vp, vp, vp, vp, i32, vp, i32, i32, i32, vp]
     L.gplhr_spmm.restype = i32
+    L.gplhr_csr_plane.argtypes = [i64, vp, vp, ctypes.POINTER(i32), vp]
+    L.gplhr_csr_plane.restype = i32
     L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
     L.gplhr_gram.restype = i32
     L.gplhr_block_update.argtypes = [i32, i64, vp, i32, i32, vp, i32, vp, i32, i32,
@@ -279,9 +282,10 @@ class Solver:
 
 
 def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
-         val: Optional[torch.Tensor] = None) -> torch.Tensor:
+         val: Optional[torch.Tensor] = None, plane: int = 0) -> torch.Tensor:
     """Y = A X with the library's CSR kernel; complex128 or complex64 blocks
-    (``val`` overrides A's values, e.g. a complex64 copy)."""
+    (``val`` overrides A's values, e.g. a complex64 copy).  ``plane`` selects
+    the row schedule (0: natural order; see csr_plane)."""
     v = A.val if val is None else val
     dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
     assert v.dtype == X.dtype and X.dim() == 2 and X.stride(1) == 1
@@ -289,8 +293,16 @@ def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
     if Y is None:
         Y = torch.empty((A.n, b), dtype=X.dtype, device=X.device)
     _check(lib().gplhr_spmm(dtype, A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
-                            X.stride(0), _ptr(Y), Y.stride(0), b, _stream_ptr()))
+                            X.stride(0), _ptr(Y), Y.stride(0), b, int(plane), _stream_ptr()))
     return Y
+
+
+def csr_plane(A: DeviceCsr) -> int:
+    """The plane-slab row schedule the solver uses for A's pattern (0: none)."""
+    out = ctypes.c_int(0)
+    _check(lib().gplhr_csr_plane(A.n, _ptr(A.row_ptr), _ptr(A.col_idx), ctypes.byref(out),
+                                 _stream_ptr()))
+    return int(out.value)
 
 
 def block_update(X: torch.Tensor, M: torch.Tensor, Y: Optional[torch.Tensor] = None,

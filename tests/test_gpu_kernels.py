@@ -62,6 +62,38 @@ def test_spmm_empty_matrix_rows(device):
     assert np.all(Y == 0)
 
 
+@pytest.mark.parametrize("N", [16, 24])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_spmm_plane_schedule(device, N, dtype):
+    # the plane-slab row order computes every row exactly as the natural order
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    csr = problems.convection_diffusion(N, (20.0, 10.0, 5.0))
+    A = G.DeviceCsr.from_host(csr)
+    assert G.csr_plane(A) == (N * N if N * N >= 512 else 0)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rng = np.random.default_rng(N)
+    for b in (1, 10, 16):
+        X = torch.as_tensor(_block(rng, csr.n, b)).to(device, tdt)
+        Y0 = G.spmm(A, X, val=A.val.to(tdt)).cpu().numpy()
+        for plane in (N * N, 8 * N, 8):
+            Y1 = G.spmm(A, X, val=A.val.to(tdt), plane=plane).cpu().numpy()
+            assert np.array_equal(Y0, Y1), (b, plane)
+
+
+def test_csr_plane_of_unstructured_patterns(device):
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(3)
+    assert G.csr_plane(G.DeviceCsr.from_host(_rand_csr(8192, rng, max_row=6))) == 0
+    # 2-D stencil: the bandwidth N gives fewer than 512 rows per plane
+    assert G.csr_plane(G.DeviceCsr.from_host(problems.convection_diffusion(64, (1.0, 1.0)))) == 0
+    with pytest.raises(Exception, match="bad arguments"):
+        A = G.DeviceCsr.from_host(problems.convection_diffusion(16, (1.0, 1.0, 1.0)))
+        import torch
+        X = torch.zeros((A.n, 4), dtype=torch.complex128, device=device)
+        G.spmm(A, X, plane=24)
+
+
 @pytest.mark.parametrize("bx,by", [(1, 1), (5, 10), (10, 10), (16, 16), (30, 48), (48, 48), (64, 64)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [1, 7, 1000, 100003])
