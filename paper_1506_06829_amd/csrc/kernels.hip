@@ -345,9 +345,9 @@ template <typename T> struct RealOf;
 template <> struct RealOf<double2> { using R = double; };
 template <> struct RealOf<float2> { using R = float; };
 
-constexpr int GM_PF = 2;   // K steps in flight per wave
+constexpr int GM_PF = 4;   // K steps in flight per wave
 
-template <typename T, int MTC, int NTC>
+template <typename T, int MTC, int NTC, int PF = GM_PF>
 __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     using R = typename RealOf<T>::R;
     __shared__ double red[2 * MTC * NTC * 256];
@@ -368,8 +368,8 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     const int64_t r = rb + 4 * h + lk;
     const int64_t span = re - rb - 4 * h;
     const int nst = span > 0 ? (int)((span + step - 1) / step) : 0;
-    R xa[GM_PF][MTC], yra[GM_PF][NTC], yia[GM_PF][NTC];
-    double scr[GM_PF], sci[GM_PF];
+    R xa[PF][MTC], yra[PF][NTC], yia[PF][NTC];
+    double scr[PF], sci[PF];
     // raw operands of the K step at `row` (row 0, always valid, past the
     // block's range; those operands are masked at use)
     auto load = [&](int p, int64_t row) {
@@ -396,10 +396,10 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
     };
     if (active) {
 #pragma unroll
-        for (int p = 0; p < GM_PF; ++p) load(p, r + (int64_t)p * step);
-        for (int j = 0; j < nst; j += GM_PF) {
+        for (int p = 0; p < PF; ++p) load(p, r + (int64_t)p * step);
+        for (int j = 0; j < nst; j += PF) {
 #pragma unroll
-            for (int p = 0; p < GM_PF; ++p) {
+            for (int p = 0; p < PF; ++p) {
                 const bool okp = (r + (int64_t)(j + p) * step) < re;
                 double xv[MTC], yv[NTC];
 #pragma unroll
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
                                                                                   acc[mt][t], 0, 0, 0);
                     }
                 }
-                load(p, r + (int64_t)(j + p + GM_PF) * step);
+                load(p, r + (int64_t)(j + p + PF) * step);
             }
         }
     }
@@ -537,7 +537,7 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T, int MTC, int NTC>
+template <typename T, int MTC, int NTC, int PF = GM_PF>
 static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
                                 int ldo, int nblk_want) {
     a.G = (a.NT + NTC - 1) / NTC;
@@ -554,7 +554,7 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
     // no block starts past the last row
     a.nblk = (int)((a.n + a.rows_per_blk - 1) / a.rows_per_blk);
-    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC>), dim3(a.nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(a.bx * a.by), dim3(256), 0, st, a.part,
                        a.nblk, a.bx, out, ldo);
@@ -572,17 +572,18 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
     a.part = reinterpret_cast<double *>(part);
     a.MT = (2 * bx + 15) / 16;
     a.NT = (2 * by + 15) / 16;
-    // tile layout per wave by the number of M tiles (measured on n = 262144);
-    // few tiles: more blocks
-    const int nb = (a.MT * a.NT <= 9) ? 512 : 256;
+    // tile layout per wave by the number of M tiles; blocks and K steps in
+    // flight measured on n = 262144 and 4096000: narrow X (at most 2 M tiles)
+    // takes 512 blocks, wider shapes 256 (one block per CU at their VGPR use)
+    const int nb = (a.MT <= 2) ? 512 : 256;
     if (a.MT <= 2 && a.NT <= 2)
         gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
     else if (a.MT <= 3)
         gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4)
         gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
-    else if (a.MT == 5)
-        gram_launch_variant<T, 5, 5>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT == 5)   // two K steps in flight: more would spill registers
+        gram_launch_variant<T, 5, 5, 2>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 6)
         gram_launch_variant<T, 6, 3>(st, a, part_cap, out, ldo, nb);
     else
@@ -1215,43 +1216,161 @@ struct ResidArgs {
     int64_t rows_per_blk;
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void resid_kernel(ResidArgs<T> a) {
-    __shared__ double2 sZ[32 * 32];
-    __shared__ double2 sl[32];
-    __shared__ double2 red[256];
+// Residual norms of the Ritz pairs (x_j = V z_j, A x_j = (C + sigma B) V z_j):
+// per column j, sum over rows of |A x_j - lambda_j B x_j|^2 and |A x_j|^2, in
+// FP64 for both block precisions.  A x and B x come from one real-split GEMM
+// on the FP64 MFMA, as in the block update: the inputs are [C V | B V] (or
+// V with the diagonal of B as a row scale), the coefficients [[Z, 0],
+// [sigma Z, Z]], so A x sits in output columns 0 .. pb-1 and B x in pb ..
+// 2 pb - 1 (pb = b rounded up to 8).  The lanes holding the real and the
+// imaginary part of one entry swap halves, each adds its rows to per-lane
+// sums, and the block sums them in a fixed order into its partial.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void resid_mfma_kernel(ResidArgs<T> a) {
+    constexpr int WOP = 8 * NT;           // 2 pb complex output columns
+    constexpr int PB = WOP / 2;
+    constexpr int NSL = PB / 8;           // slabs of 8 input columns per term
+    extern __shared__ double2 sh_resid_raw[];
+    double2 *sM = sh_resid_raw;           // 2 PB x WOP, row-major
     const int b = a.b;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < b * b; e += 256) sZ[e] = a.Zr[e];
-    if (tid < b) sl[tid] = a.lam[tid];
+    for (int e = threadIdx.x; e < 2 * PB * WOP; e += 256) {
+        const int j = e / WOP, c = e - j * WOP;
+        double2 v = make_double2(0.0, 0.0);
+        if (j < PB) {
+            if (j < b && c < b) v = a.Zr[j + c * b];
+        } else if (j - PB < b) {
+            const int jj = j - PB;
+            if (c < b) v = cmul(a.sigma, a.Zr[jj + c * b]);
+            else if (c >= PB && c - PB < b) v = a.Zr[jj + (c - PB) * b];
+        }
+        sM[e] = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool odd = li & 1;
+    double2 lamc[NT / 2];
+#pragma unroll
+    for (int nt = 0; nt < NT / 2; ++nt) {
+        const int c = nt * 8 + (li >> 1);
+        lamc[nt] = c < b ? a.lam[c] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
-    const int rpt = 256 / b;        // rows handled concurrently
-    const int r_off = tid / b, j = tid - r_off * b;
-    double2 acc = make_double2(0.0, 0.0);
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_blk;
-    const int64_t r1 = min(a.n, r0 + a.rows_per_blk);
-    if (r_off < rpt) {
-        for (int64_t r = r0 + r_off; r < r1; r += rpt) {
-            double2 ax = make_double2(0.0, 0.0), bx = make_double2(0.0, 0.0);
-            const double2 sc = a.bscale ? to_d(a.bscale[r]) : make_double2(1.0, 0.0);
-            for (int c = 0; c < b; ++c) {
-                const double2 cv = to_d(a.CV[r * a.ldc + c]);
-                double2 bvv = a.bv ? to_d(a.bv[r * a.ldb + c]) : cmul(sc, to_d(a.V[r * a.ldv + c]));
-                const double2 z = sZ[c + j * b];
-                cfma(bx, bvv, z);
-                cfma(ax, cadd(cv, cmul(a.sigma, bvv)), z);
+    const T *in1 = a.bv ? a.bv : a.V;
+    const int ld1 = a.bv ? a.ldb : a.ldv;
+    const bool scale1 = !a.bv && a.bscale;
+    const int64_t stride = (int64_t)gridDim.x * 64;
+    // slab q of a row group: term q / NSL (0: C V, 1: B V), slab q % NSL
+    struct Cur {
+        int64_t g;
+        int q;
+    };
+    auto next = [&](Cur c) {
+        if (++c.q == 2 * NSL) { c.q = 0; c.g += stride; }
+        return c;
+    };
+    T bx[2][2];
+    T brs[2];
+    auto load = [&](int p, const Cur &c) {
+        const int t = c.q / NSL, col0 = (c.q - t * NSL) * 8 + 2 * lk;
+        const int ca = col0 < b ? col0 : 0, cb = col0 + 1 < b ? col0 + 1 : 0;
+        int64_t row = c.g + li;
+        row = row < a.n ? row : a.n - 1;
+        const T *rp = t == 0 ? a.CV + row * a.ldc : in1 + row * ld1;
+        bx[p][0] = rp[ca];
+        bx[p][1] = rp[cb];
+        if (t == 1 && scale1) brs[p] = a.bscale[row];
+    };
+    d4v acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = d4v{0.0, 0.0, 0.0, 0.0};
+    double sr[NT / 2], sa[NT / 2];
+#pragma unroll
+    for (int nt = 0; nt < NT / 2; ++nt) sr[nt] = sa[nt] = 0.0;
+    auto multiply = [&](int p, const Cur &c) {
+        const int t = c.q / NSL, col0 = (c.q - t * NSL) * 8 + 2 * lk;
+        const double2 *mrow = sM + (int64_t)(t * PB + col0) * WOP + (li >> 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double2 m[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) m[nt] = mrow[h * WOP + nt * 8];
+            double2 x = to_d(bx[p][h]);
+            if (t == 1 && scale1) x = cmul(to_d(brs[p]), x);
+            if (col0 + h >= b) x = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int part = 0; part < 2; ++part) {
+                const double av = part == 0 ? x.x : x.y;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const double bv =
+                        part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
+                    acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
+                }
             }
-            const double2 rr = csub(ax, cmul(sl[j], bx));
-            acc.x += rr.x * rr.x + rr.y * rr.y;
-            acc.y += ax.x * ax.x + ax.y * ax.y;
+        }
+    };
+    auto finish = [&](int64_t g) {
+#pragma unroll
+        for (int nt = 0; nt < NT / 2; ++nt) {
+            double oa[4], ob[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                oa[v] = __shfl_xor(acc[nt][v], 1);
+                ob[v] = __shfl_xor(acc[nt + NT / 2][v], 1);
+            }
+            const int c = nt * 8 + (li >> 1);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int v = 2 * u + (odd ? 1 : 0);
+                const int64_t row = g + 4 * v + lk;    // FP64 MFMA: register v holds row 4v + k
+                if (row < a.n && c < b) {
+                    const double2 ax = odd ? make_double2(oa[v], acc[nt][v]) : make_double2(acc[nt][v], oa[v]);
+                    const double2 bxv = odd ? make_double2(ob[v], acc[nt + NT / 2][v])
+                                            : make_double2(acc[nt + NT / 2][v], ob[v]);
+                    const double2 r = csub(ax, cmul(lamc[nt], bxv));
+                    sr[nt] += r.x * r.x + r.y * r.y;
+                    sa[nt] += ax.x * ax.x + ax.y * ax.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = d4v{0.0, 0.0, 0.0, 0.0};
+    };
+    Cur c{((int64_t)blockIdx.x * 4 + wave) * 16, 0};
+    Cur q[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        q[p] = c;
+        if (c.g < a.n) load(p, c);
+        c = next(c);
+    }
+    while (q[0].g < a.n) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const Cur cc = q[p];
+            if (cc.g < a.n) {
+                multiply(p, cc);
+                if (cc.q == 2 * NSL - 1) finish(cc.g);
+                q[p] = c;
+                if (c.g < a.n) load(p, c);
+                c = next(c);
+            }
         }
     }
-    red[tid] = acc;
+    __syncthreads();   // sM is reused for the block reduction
+    double2 *red = sh_resid_raw;   // [wave][lane][NT / 2]
+#pragma unroll
+    for (int nt = 0; nt < NT / 2; ++nt)
+        red[(wave * 64 + lane) * (NT / 2) + nt] = make_double2(sr[nt], sa[nt]);
     __syncthreads();
-    if (tid < b) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int r = 0; r < rpt; ++r) s = cadd(s, red[r * b + tid]);
-        a.part[(int64_t)tid * a.nblk + blockIdx.x] = s;
+    if ((int)threadIdx.x < b) {
+        const int j = threadIdx.x, nt = j / 8, lh = j % 8;
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int w = 0; w < 4; ++w)
+            for (int k = 0; k < 4; ++k)
+                for (int o = 0; o < 2; ++o)
+                    s2 = cadd(s2, red[(w * 64 + 2 * lh + o + 16 * k) * (NT / 2) + nt]);
+        a.part[(int64_t)j * a.nblk + blockIdx.x] = s2;
     }
 }
 
@@ -1259,12 +1378,18 @@ template <typename T>
 int launch_resid_partials(hipStream_t st, int64_t n, int b, const T *CV, int ldc, const T *V,
                           int ldv, const T *bv, int ldb, const T *bscale, double2 sigma,
                           const double2 *Zr, const double2 *lam, double2 *part, int max_blocks) {
-    if (b < 1 || b > 32) throw Error(-1, "resid: width out of range");
+    // the solver's block is at most 16 wide
+    if (b < 1 || b > 16) throw Error(-1, "resid: width out of range");
     ResidArgs<T> a{n, b, CV, ldc, V, ldv, bv, ldb, bscale, sigma, Zr, lam, part, 0, 0};
-    int nblk = (int)std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n + 255) / 256));
+    const int nblk = (int)std::min<int64_t>(max_blocks, std::max<int64_t>(1, (n + 63) / 64));
     a.nblk = nblk;
-    a.rows_per_blk = (n + nblk - 1) / nblk;
-    hipLaunchKernelGGL((resid_kernel<T>), dim3(nblk), dim3(256), 0, st, a);
+    a.rows_per_blk = 0;
+    const int pb = pad8(b), nt = pb / 4;
+    const size_t shmem = std::max(sizeof(double2) * 2 * pb * 2 * pb, sizeof(double2) * 256 * (nt / 2));
+    if (nt == 2)
+        hipLaunchKernelGGL((resid_mfma_kernel<T, 2>), dim3(nblk), dim3(256), shmem, st, a);
+    else
+        hipLaunchKernelGGL((resid_mfma_kernel<T, 4>), dim3(nblk), dim3(256), shmem, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     return nblk;
 }

@@ -289,6 +289,35 @@ def test_full_size_160cube_properties(device, precision):
     np.testing.assert_allclose(np.sort(out["rho"]), np.sort(rho), rtol=1e-6 if precision == "fp64" else 1e-2)
 
 
+@pytest.mark.parametrize("name,scale,bb", [("c1", None, 1), ("d1", 3000, 6), ("c4", 600, 10),
+                                           ("d1", 3000, 16)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reported_residuals_match_definition(device, name, scale, bb, precision):
+    # the residual norms the library reports (its convergence test) against
+    # the definition on the CPU, for both width classes of the residual kernel
+    # (8 and 16 padded columns) and B = I, diagonal B and sparse B
+    p = problems.config(name, scale)
+    p.k = p.block = bb
+    rng = np.random.default_rng(bb)
+    p.V0 = (rng.standard_normal((p.n, bb)) + 1j * rng.standard_normal((p.n, bb))) / np.sqrt(2)
+    s, _, _ = gpu_solver(p, precision=precision, tol=0.0, max_iter=2, switch_tol=0.0,
+                         stall_window=10**6)
+    s.iterate(2)
+    out = s.schur()
+    s.close()
+    V = out["V"].cpu().numpy()
+    A = p.A.to_scipy()
+    B = sp.identity(p.n, format="csr") if p.B is None else p.B.to_scipy()
+    AV, BV = A @ V, B @ V
+    lam, Zr = sla.eig(V.conj().T @ AV, V.conj().T @ BV)
+    order = np.argsort(np.abs(lam - p.sigma), kind="stable")
+    lam, Zr = lam[order], Zr[:, order] / np.linalg.norm(Zr[:, order], axis=0)
+    Ax, Bx = AV @ Zr, BV @ Zr
+    rho = np.linalg.norm(Ax - Bx * lam[None, :], axis=0) / np.linalg.norm(Ax, axis=0)
+    np.testing.assert_allclose(np.sort(out["rho"]), np.sort(rho),
+                               rtol=1e-6 if precision == "fp64" else 1e-2)
+
+
 @pytest.mark.parametrize("k,block,locking", [(1, 1, False), (3, 6, True), (3, 6, False)])
 def test_converged_parity_block_shapes(device, k, block, locking):
     # one wanted pair with a one-column block, and a block wider than k (the k
