@@ -576,9 +576,18 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
     // flight measured on n = 262144 and 4096000: narrow X (at most 2 M tiles)
     // takes 512 blocks, wider shapes 256 (one block per CU at their VGPR use)
     const int nb = (a.MT <= 2) ? 512 : 256;
-    if (a.MT <= 2 && a.NT <= 2)
-        gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
-    else if (a.MT <= 3)
+    if (a.NT <= 2) {
+        // Y at most 16 columns wide (the projections against the trial or
+        // test basis): MT x 2 tiles per wave, rows split over the 4 waves; a
+        // wider compiled tile set would only cost registers (4096000 rows:
+        // 40 x 10 924 -> 633 us, 30 x 10 686 -> 526 us)
+        if (a.MT <= 2) gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 3) gram_launch_variant<T, 3, 2>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 4) gram_launch_variant<T, 4, 2>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 5) gram_launch_variant<T, 5, 2>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 6) gram_launch_variant<T, 6, 2>(st, a, part_cap, out, ldo, nb);
+        else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+    } else if (a.MT <= 3)
         gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4)
         gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
