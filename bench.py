@@ -92,6 +92,70 @@ def spmm_hbm(G, torch, csr, b, dtype, reps=20, plane=None):
     return dict(ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6, plane=plane)
 
 
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (MFMA FP32 rate of the complex64 updates)
+
+
+def kernel_rooflines(G, torch):
+    """Event-timed block updates and Grams at the 160^3 and d1 sizes, each
+    against the roofline that bounds it: bytes / 8 TB/s for the HBM-bound
+    shapes, flops / the FP64 (or FP32) peak for the wide ones, whichever
+    takes longer at peak."""
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    out = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for n, dt, wx, wy, beta in ((4096000, "c128", 16, 16, 1.0), (4096000, "c128", 64, 32, 0.0),
+                                (4096000, "c64", 64, 32, 0.0), (262144, "c128", 10, 10, 1.0)):
+        tdt = torch.complex128 if dt == "c128" else torch.complex64
+        e = 16 if dt == "c128" else 8
+        X = torch.randn(n, wx, dtype=tdt, device="cuda", generator=gen)
+        Y = torch.randn(n, wy, dtype=tdt, device="cuda", generator=gen)
+        # stored column-major already, so the binding makes no copy per call
+        M = torch.randn(wy, wx, dtype=torch.complex128, device="cuda", generator=gen).t()
+        ms = timed(lambda: G.block_update(X, M, Y, beta=beta))
+        nbytes = n * (wx + wy * (2 if beta else 1)) * e
+        flops = 8.0 * n * wx * wy
+        peak_tf = FP64_PEAK_TFLOPS if dt == "c128" else FP32_PEAK_TFLOPS
+        t_mem, t_fl = nbytes / (HBM_PEAK_GBS * 1e6), flops / (peak_tf * 1e9)
+        if t_mem >= t_fl:
+            rf = {"bound": "hbm", "achieved": nbytes / ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            rf = {"bound": "mfma", "achieved": flops / ms / 1e9, "peak": peak_tf, "unit": "TFLOP/s"}
+        rf["frac"] = rf["achieved"] / rf["peak"]
+        out.append(dict(kernel=f"block update {dt} {wx}->{wy}" + (" (beta=1)" if beta else ""), n=n,
+                        ms=ms, **rf))
+        del X, Y, M
+    for n, dt, bx, by in ((4096000, "c128", 64, 64), (4096000, "c128", 16, 16), (262144, "c128", 40, 40),
+                          (262144, "c128", 10, 10)):
+        tdt = torch.complex128 if dt == "c128" else torch.complex64
+        X = torch.randn(n, bx, dtype=tdt, device="cuda", generator=gen)
+        Y = torch.randn(n, by, dtype=tdt, device="cuda", generator=gen)
+        ms = timed(lambda: G.gram(X, Y))
+        nbytes = n * (bx + by) * 16
+        flops = 8.0 * n * bx * by
+        t_mem, t_fl = nbytes / (HBM_PEAK_GBS * 1e6), flops / (FP64_PEAK_TFLOPS * 1e9)
+        if t_mem >= t_fl:
+            rf = {"bound": "hbm", "achieved": nbytes / ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            rf = {"bound": "mfma", "achieved": flops / ms / 1e9, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        rf["frac"] = rf["achieved"] / rf["peak"]
+        out.append(dict(kernel=f"Gram {dt} {bx}x{by} (FP64 MFMA, incl. the partial reduction)", n=n, ms=ms, **rf))
+        del X, Y
+    torch.cuda.empty_cache()
+    return out
+
+
 def named_iteration_times(G, torch, name, scale, its, precisions):
     from paper_1506_06829_amd import problems
     p = problems.config(name, scale)
@@ -338,6 +402,10 @@ def main():
     log(f"[bench] SpMM 160^3 b=16: c64 {sp64['gbs']:.0f} GB/s ({sp64['ms']:.3f} ms), "
         f"c128 {sp128['gbs']:.0f} GB/s ({sp128['ms']:.3f} ms)")
     del c5A
+    rooflines = kernel_rooflines(G, torch)
+    for r in rooflines:
+        log(f"[bench] {r['kernel']} n={r['n']}: {r['ms']*1e3:.0f} us, {r['achieved']:.0f} {r['unit']} "
+            f"({r['frac']:.2f} of {r['bound']} peak)")
 
     nxt = None
     if not args.no_next:
@@ -397,6 +465,7 @@ def main():
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],
                  "c128_ms": sp128["ms"], "in_solve_ms_per_launch": spmm_ms_per,
                  "in_solve_bytes_per_launch": spmm_bytes_per},
+        "other_kernel_rooflines": rooflines,
         "solve_kernel_ms": {"spmm": stats_m["spmm_ms"], "gram": stats_m["gram_ms"],
                             "update": stats_m["update_ms"], "host_small_step": stats_m["small_host_ms"]},
         "next_rows": nxt,

@@ -17,7 +17,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libgplhr.so"
 
-SOURCES = ["kernels.hip", "driver.hip", "capi.cpp", "small_dense.cpp"]
+SOURCES = ["kernels.hip", "driver.hip", "capi.cpp", "memory.cpp", "small_dense.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -228,7 +228,8 @@ gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad
         {
             std::vector<double2> P(k * k, make_double2(0.0, 0.0));
             for (int e = 0; e < k; ++e) P[perm[e] + e * k] = make_double2(1.0, 0.0);
-            GPLHR_HIP_CHECK(hipMemcpy(c.coefY, P.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice));
+            GPLHR_HIP_CHECK(hipMemcpyAsync(c.coefY, P.data(), sizeof(double2) * k * k, hipMemcpyHostToDevice, st));
+            GPLHR_HIP_CHECK(hipStreamSynchronize(st));
             gplhr::UpdTerm<double2> t;
             t.in = Y; t.ld = k; t.col = 0; t.w = k; t.M = c.coefY; t.ldm = k;
             gplhr::launch_update<double2>(st, n, Y, k, k, 0, k, 0, make_double2(0, 0), 1, &t);

@@ -94,8 +94,10 @@ struct Ctx {
     double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
     double2 *gmH = nullptr, *gmY = nullptr;   // block GMRES small factors (device)
     double2 *hgm = nullptr;                   // their pinned host staging
+    size_t hgm_bytes = 0;
     int *dstatus = nullptr;
     double2 *hpin = nullptr;   // pinned host staging
+    size_t hpin_bytes = 0;
 
     // host state of the iteration
     small::Mat MA, MB, RA, RB, Zr_h;

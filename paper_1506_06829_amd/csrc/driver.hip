@@ -28,20 +28,12 @@ static double2 to_d2(cd z) { return make_double2(z.real(), z.imag()); }
 // allocation helpers
 // ---------------------------------------------------------------------------
 template <typename P>
-static void dalloc(P **p, size_t count) {
-    void *q = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&q, count * sizeof(P));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(-2, "device allocation of " + std::to_string(count * sizeof(P)) +
-                            " bytes failed: " + hipGetErrorString(e));
-    }
-    *p = static_cast<P *>(q);
+static void dalloc(P **p, size_t count, hipStream_t st) {
+    *p = static_cast<P *>(dev_alloc((count ? count : 1) * sizeof(P), st));
 }
 template <typename P>
-static void dfree(P *&p) {
-    if (p) (void)hipFree((void *)p);
+static void dfree(P *&p, hipStream_t st) {
+    dev_free((void *)p, st);
     p = nullptr;
 }
 
@@ -52,17 +44,20 @@ Ctx::~Ctx() {
             (void)hipEventDestroy(ev.second);
         }
     }
-    dfree(c_rp); dfree(c_ci); dfree(c_val); dfree(c_val32);
-    dfree(a_rp); dfree(a_ci); dfree(a_val);
-    dfree(b_rp); dfree(b_ci); dfree(b_val); dfree(b_val32);
-    dfree(bd); dfree(bd32); dfree(dinv); dfree(dinv32); dfree(dw); dfree(dw32);
-    for (Work<double2> *w : {&wd}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
-    for (Work<float2> *w : {&wf}) { dfree(w->Z); dfree(w->CZ); dfree(w->BZ); dfree(w->U); dfree(w->R); dfree(w->J1); dfree(w->J2); dfree(w->G); dfree(w->Gz); dfree(w->Gx); dfree(w->Vd); dfree(w->Qd); }
-    dfree(part); dfree(g0); dfree(g1); dfree(rinv); dfree(coefY); dfree(coefL);
-    dfree(M1); dfree(M2); dfree(M1s); dfree(M2s); dfree(F1); dfree(F2); dfree(dZr); dfree(dlam); dfree(rnorm);
-    dfree(dstatus); dfree(gmH); dfree(gmY);
-    if (hpin) (void)hipHostFree(hpin);
-    if (hgm) (void)hipHostFree(hgm);
+    dfree(c_rp, st); dfree(c_ci, st); dfree(c_val, st); dfree(c_val32, st);
+    dfree(a_rp, st); dfree(a_ci, st); dfree(a_val, st);
+    dfree(b_rp, st); dfree(b_ci, st); dfree(b_val, st); dfree(b_val32, st);
+    dfree(bd, st); dfree(bd32, st); dfree(dinv, st); dfree(dinv32, st); dfree(dw, st); dfree(dw32, st);
+    for (Work<double2> *w : {&wd}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
+    for (Work<float2> *w : {&wf}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
+    dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(coefL, st);
+    dfree(M1, st); dfree(M2, st); dfree(M1s, st); dfree(M2s, st); dfree(F1, st); dfree(F2, st); dfree(dZr, st); dfree(dlam, st); dfree(rnorm, st);
+    dfree(dstatus, st); dfree(gmH, st); dfree(gmY, st);
+    // the staging buffers go back to the free list only once the stream has
+    // finished with them (dev_free above waited for it)
+    (void)hipStreamSynchronize(st);
+    pinned_free(hpin, hpin_bytes);
+    pinned_free(hgm, hgm_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -765,7 +760,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     if (bad_rows) throw Error(-1, "A: " + std::to_string(bad_rows) + " rows with unsorted, duplicate or out-of-range columns");
     if (bad_vals) throw Error(-6, "A: non-finite values");
     a_nnz = A->nnz;
-    dalloc(&a_rp, n + 1); dalloc(&a_ci, a_nnz); dalloc(&a_val, a_nnz);
+    dalloc(&a_rp, n + 1, st); dalloc(&a_ci, a_nnz, st); dalloc(&a_val, a_nnz, st);
     GPLHR_HIP_CHECK(hipMemcpyAsync(a_rp, A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(a_ci, A->col_idx, sizeof(int32_t) * a_nnz, hipMemcpyDeviceToDevice, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(a_val, A->val, sizeof(double2) * a_nnz, hipMemcpyDeviceToDevice, st));
@@ -782,14 +777,14 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         if (bad_rows) throw Error(-1, "B: " + std::to_string(bad_rows) + " malformed rows");
         if (bad_vals) throw Error(-6, "B: non-finite values");
         b_nnz = B->nnz;
-        dalloc(&b_rp, n + 1); dalloc(&b_ci, b_nnz); dalloc(&b_val, b_nnz);
+        dalloc(&b_rp, n + 1, st); dalloc(&b_ci, b_nnz, st); dalloc(&b_val, b_nnz, st);
         GPLHR_HIP_CHECK(hipMemcpyAsync(b_rp, B->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
         GPLHR_HIP_CHECK(hipMemcpyAsync(b_ci, B->col_idx, sizeof(int32_t) * b_nnz, hipMemcpyDeviceToDevice, st));
         GPLHR_HIP_CHECK(hipMemcpyAsync(b_val, B->val, sizeof(double2) * b_nnz, hipMemcpyDeviceToDevice, st));
         const int64_t nondiag = csr_count_nondiag_rows(st, n, b_rp, b_ci);
         if (nondiag == 0) {
             bk = B_DIAG;
-            dalloc(&bd, n);
+            dalloc(&bd, n, st);
             GPLHR_HIP_CHECK(hipMemcpyAsync(bd, b_val, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
         } else {
             bk = B_SPARSE;
@@ -802,20 +797,20 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     if (bk == B_SPARSE) b_plane = spmm_plane(st, n, b_rp, b_ci);
     if (ik != GPLHR_PRECOND_NONE) {
         double2 *dg = nullptr;
-        dalloc(&dg, n);
+        dalloc(&dg, n, st);
         const int64_t zeros = extract_diag(st, n, c_rp, c_ci, c_val, dg);
         if (zeros) {
-            dfree(dg);
+            dfree(dg, st);
             throw Error(-5, "diag(A - sigma B) has " + std::to_string(zeros) + " zero entries");
         }
-        dalloc(&dinv, n);
+        dalloc(&dinv, n, st);
         launch_recip_scaled(st, n, dg, make_double2(1.0, 0.0), dinv);
         if (ik == GPLHR_PRECOND_JACOBI) {
-            dalloc(&dw, n);
+            dalloc(&dw, n, st);
             launch_recip_scaled(st, n, dg, make_double2(pre.omega, 0.0), dw);
         }
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
-        dfree(dg);
+        dfree(dg, st);
     }
     mixed = (opt.precision == GPLHR_MIXED);
     phase = mixed ? 0 : 1;
@@ -823,7 +818,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     // workspace
     const size_t blk_s = (size_t)n * smax, blk_b = (size_t)n * b;
     wd.cval = c_val; wd.bval = b_val; wd.bd = bd; wd.dinv = dinv; wd.dw = dw;
-    dalloc(&wd.Z, blk_s); dalloc(&wd.CZ, blk_s); dalloc(&wd.U, blk_s);
+    dalloc(&wd.Z, blk_s, st); dalloc(&wd.CZ, blk_s, st); dalloc(&wd.U, blk_s, st);
     defl_k = opt.defl_k;
     if (defl_k < 0 || defl_k > 64) throw Error(-1, "defl_k must be in [0, 64]");
     if (defl_k) {
@@ -831,51 +826,52 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
             throw Error(-1, "deflation needs V1 (and Q1 when B != I)");
         if (defl_k + smax > n) throw Error(-1, "defl_k + (m+3)*block exceeds n");
         const void *q1 = (bk == B_IDENT) ? opt.defl_V : opt.defl_Q;
-        dalloc(&wd.Vd, (size_t)n * defl_k);
-        dalloc(&wd.Qd, (size_t)n * defl_k);
+        dalloc(&wd.Vd, (size_t)n * defl_k, st);
+        dalloc(&wd.Qd, (size_t)n * defl_k, st);
         GPLHR_HIP_CHECK(hipMemcpyAsync(wd.Vd, opt.defl_V, sizeof(double2) * n * defl_k, hipMemcpyDeviceToDevice, st));
         GPLHR_HIP_CHECK(hipMemcpyAsync(wd.Qd, q1, sizeof(double2) * n * defl_k, hipMemcpyDeviceToDevice, st));
     }
-    if (bexp()) dalloc(&wd.BZ, blk_s);
-    dalloc(&wd.R, blk_b);
+    if (bexp()) dalloc(&wd.BZ, blk_s, st);
+    dalloc(&wd.R, blk_b, st);
     const bool jac2 = (ik == GPLHR_PRECOND_JACOBI && pre.sweeps > 1);
     const bool gm = (pre.kind == GPLHR_PRECOND_GMRES);
     const size_t blk_g = gm ? (size_t)n * (pre.steps + 1) * b : 0;
-    if (jac2) { dalloc(&wd.J1, blk_b); dalloc(&wd.J2, blk_b); }
-    if (gm) { dalloc(&wd.G, blk_g); dalloc(&wd.Gz, blk_b); dalloc(&wd.Gx, blk_b); }
+    if (jac2) { dalloc(&wd.J1, blk_b, st); dalloc(&wd.J2, blk_b, st); }
+    if (gm) { dalloc(&wd.G, blk_g, st); dalloc(&wd.Gz, blk_b, st); dalloc(&wd.Gx, blk_b, st); }
     if (mixed) {
-        dalloc(&c_val32, c_nnz);
+        dalloc(&c_val32, c_nnz, st);
         launch_c128_to_c64_flat(st, c_nnz, c_val, c_val32);
         wf.cval = c_val32;
-        if (bk == B_SPARSE) { dalloc(&b_val32, b_nnz); launch_c128_to_c64_flat(st, b_nnz, b_val, b_val32); wf.bval = b_val32; }
-        if (bk == B_DIAG) { dalloc(&bd32, n); launch_c128_to_c64_flat(st, n, bd, bd32); wf.bd = bd32; }
-        if (dinv) { dalloc(&dinv32, n); launch_c128_to_c64_flat(st, n, dinv, dinv32); wf.dinv = dinv32; }
-        if (dw) { dalloc(&dw32, n); launch_c128_to_c64_flat(st, n, dw, dw32); wf.dw = dw32; }
-        dalloc(&wf.Z, blk_s); dalloc(&wf.CZ, blk_s); dalloc(&wf.U, blk_s);
-        if (bexp()) dalloc(&wf.BZ, blk_s);
+        if (bk == B_SPARSE) { dalloc(&b_val32, b_nnz, st); launch_c128_to_c64_flat(st, b_nnz, b_val, b_val32); wf.bval = b_val32; }
+        if (bk == B_DIAG) { dalloc(&bd32, n, st); launch_c128_to_c64_flat(st, n, bd, bd32); wf.bd = bd32; }
+        if (dinv) { dalloc(&dinv32, n, st); launch_c128_to_c64_flat(st, n, dinv, dinv32); wf.dinv = dinv32; }
+        if (dw) { dalloc(&dw32, n, st); launch_c128_to_c64_flat(st, n, dw, dw32); wf.dw = dw32; }
+        dalloc(&wf.Z, blk_s, st); dalloc(&wf.CZ, blk_s, st); dalloc(&wf.U, blk_s, st);
+        if (bexp()) dalloc(&wf.BZ, blk_s, st);
         if (defl_k) {
-            dalloc(&wf.Vd, (size_t)n * defl_k);
-            dalloc(&wf.Qd, (size_t)n * defl_k);
+            dalloc(&wf.Vd, (size_t)n * defl_k, st);
+            dalloc(&wf.Qd, (size_t)n * defl_k, st);
             launch_c128_to_c64_flat(st, (int64_t)n * defl_k, wd.Vd, wf.Vd);
             launch_c128_to_c64_flat(st, (int64_t)n * defl_k, wd.Qd, wf.Qd);
         }
-        dalloc(&wf.R, blk_b);
-        if (jac2) { dalloc(&wf.J1, blk_b); dalloc(&wf.J2, blk_b); }
-        if (gm) { dalloc(&wf.G, blk_g); dalloc(&wf.Gz, blk_b); dalloc(&wf.Gx, blk_b); }
+        dalloc(&wf.R, blk_b, st);
+        if (jac2) { dalloc(&wf.J1, blk_b, st); dalloc(&wf.J2, blk_b, st); }
+        if (gm) { dalloc(&wf.G, blk_g, st); dalloc(&wf.Gz, blk_b, st); dalloc(&wf.Gx, blk_b, st); }
     }
-    dalloc(&part, PART_CAP);
-    dalloc(&g0, 64 * 64); dalloc(&g1, 64 * 64); dalloc(&rinv, 64 * 64);
-    dalloc(&coefY, 64 * 64); dalloc(&coefL, 64 * 64);
-    dalloc(&M1, 64 * 64); dalloc(&M2, 64 * 64); dalloc(&M1s, 64 * 64); dalloc(&M2s, 64 * 64); dalloc(&F1, 64 * 64); dalloc(&F2, 64 * 64);
-    dalloc(&dZr, 64 * 64); dalloc(&dlam, 64); dalloc(&rnorm, 64); dalloc(&dstatus, 1);
+    dalloc(&part, PART_CAP, st);
+    dalloc(&g0, 64 * 64, st); dalloc(&g1, 64 * 64, st); dalloc(&rinv, 64 * 64, st);
+    dalloc(&coefY, 64 * 64, st); dalloc(&coefL, 64 * 64, st);
+    dalloc(&M1, 64 * 64, st); dalloc(&M2, 64 * 64, st); dalloc(&M1s, 64 * 64, st); dalloc(&M2s, 64 * 64, st); dalloc(&F1, 64 * 64, st); dalloc(&F2, 64 * 64, st);
+    dalloc(&dZr, 64 * 64, st); dalloc(&dlam, 64, st); dalloc(&rnorm, 64, st); dalloc(&dstatus, 1, st);
     if (gm) {
-        dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT);
-        dalloc(&gmY, 64 * 16);
-        GPLHR_HIP_CHECK(hipHostMalloc((void **)&hgm, sizeof(double2) * (pre.steps + 1) * 4 * GM_SLOT,
-                                      hipHostMallocDefault));
+        dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT, st);
+        dalloc(&gmY, 64 * 16, st);
+        hgm_bytes = sizeof(double2) * (pre.steps + 1) * 4 * GM_SLOT;
+        hgm = static_cast<double2 *>(pinned_alloc(hgm_bytes));
     }
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
-    GPLHR_HIP_CHECK(hipHostMalloc((void **)&hpin, sizeof(double2) * 4 * 64 * 64 + 4096, hipHostMallocDefault));
+    hpin_bytes = sizeof(double2) * 4 * 64 * 64 + 4096;
+    hpin = static_cast<double2 *>(pinned_alloc(hpin_bytes));
 
     // V0 -> Z(:, 0:b), then steps 1-4
     if (opt.V0)
@@ -986,12 +982,12 @@ void Ctx::eigvecs(double2 *X) {
     t.col = 0; t.w = b; t.M = dZr; t.ldm = b;
     if (phase == 0) {
         double2 *tmp = nullptr;
-        dalloc(&tmp, (size_t)n * b);
+        dalloc(&tmp, (size_t)n * b, st);
         launch_c64_to_c128(st, n, b, wf.Z, smax, tmp, b);
         t.in = tmp; t.ld = b;
         launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
-        dfree(tmp);
+        dfree(tmp, st);
     } else {
         t.in = wd.Z; t.ld = smax;
         launch_update<double2>(st, n, X, k, k, 0, k, 0, make_double2(0, 0), 1, &t);

@@ -22,6 +22,15 @@ struct Error : std::runtime_error {
             throw ::gplhr::Error(-3, std::string(#expr) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+// Library workspace (memory.cpp): device memory through a cache of freed
+// blocks (kept for later handles) and pinned host buffers from a free list.
+// dev_free waits for the work queued on st before the block can be reused;
+// pinned_free takes the size given to pinned_alloc.
+void *dev_alloc(size_t bytes, hipStream_t st);
+void dev_free(void *p, hipStream_t st);
+void *pinned_alloc(size_t bytes);
+void pinned_free(void *p, size_t bytes);
+
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels.hip).  T is double2 (complex128) or float2
 // (complex64).  All blocks are row-major with explicit leading dimensions.
@@ -115,7 +124,7 @@ void csr_validate(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *c
 int64_t csr_count_nondiag_rows(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci);
 
 // Union-pattern C = A - sigma B.  bkind: 0 identity, 1 sparse (rp/ci/val of
-// B).  Allocates rp/ci/val of C (device) and returns nnz(C).
+// B).  Allocates rp/ci/val of C with dev_alloc on st and returns nnz(C).
 int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32_t *aci,
                       const double2 *aval, int bkind, const int32_t *brp, const int32_t *bci,
                       const double2 *bval, double2 sigma, int32_t **crp, int32_t **cci,

@@ -1593,9 +1593,8 @@ int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32
                       const double2 *aval, int bkind, const int32_t *brp, const int32_t *bci,
                       const double2 *bval, double2 sigma, int32_t **crp, int32_t **cci,
                       double2 **cval) {
-    int32_t *cnt = nullptr, *rp = nullptr;
-    GPLHR_HIP_CHECK(hipMalloc((void **)&cnt, sizeof(int32_t) * (n + 1)));
-    GPLHR_HIP_CHECK(hipMalloc((void **)&rp, sizeof(int32_t) * (n + 1)));
+    int32_t *cnt = static_cast<int32_t *>(dev_alloc(sizeof(int32_t) * (n + 1), st));
+    int32_t *rp = static_cast<int32_t *>(dev_alloc(sizeof(int32_t) * (n + 1), st));
     hipLaunchKernelGGL(union_count_kernel, dim3(ceil_div_i(n + 1, 256)), dim3(256), 0, st, n, arp,
                        aci, bkind, brp, bci, cnt);
     GPLHR_HIP_CHECK(hipGetLastError());
@@ -1603,11 +1602,9 @@ int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32
     int32_t nnz = 0;
     GPLHR_HIP_CHECK(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
-    GPLHR_HIP_CHECK(hipFree(cnt));
-    int32_t *ci = nullptr;
-    double2 *val = nullptr;
-    GPLHR_HIP_CHECK(hipMalloc((void **)&ci, sizeof(int32_t) * std::max<int64_t>(1, nnz)));
-    GPLHR_HIP_CHECK(hipMalloc((void **)&val, sizeof(double2) * std::max<int64_t>(1, nnz)));
+    dev_free(cnt, st);
+    int32_t *ci = static_cast<int32_t *>(dev_alloc(sizeof(int32_t) * std::max<int64_t>(1, nnz), st));
+    double2 *val = static_cast<double2 *>(dev_alloc(sizeof(double2) * std::max<int64_t>(1, nnz), st));
     hipLaunchKernelGGL(union_fill_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, arp, aci,
                        aval, bkind, brp, bci, bval, sigma, rp, ci, val);
     GPLHR_HIP_CHECK(hipGetLastError());
