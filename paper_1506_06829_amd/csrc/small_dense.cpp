@@ -122,7 +122,7 @@ static inline void rot_cols(Mat &M, int p, int q, int r0, int r1, const Rot &G) 
 
 static void hessenberg(Mat &H, Mat &Y) {
     const int n = H.r;
-    std::vector<cd> v(n);
+    std::vector<cd> v(n), d(n), e(n);
     for (int j = 0; j + 2 < n; ++j) {
         double tail = 0.0;
         for (int i = j + 2; i < n; ++i) tail += std::norm(H(i, j));
@@ -145,17 +145,27 @@ static void hessenberg(Mat &H, Mat &Y) {
             for (int i = j + 1; i < n; ++i) H(i, c) -= v[i] * d;
         }
         // H <- H (I - tau v v^H), Y <- Y (I - tau v v^H) on columns j+1..n-1
-        for (int r = 0; r < n; ++r) {
-            cd d(0.0, 0.0), e(0.0, 0.0);
-            for (int i = j + 1; i < n; ++i) {
-                d += H(r, i) * v[i];
-                e += Y(r, i) * v[i];
+        // (row sums accumulated column by column: contiguous in memory)
+        std::fill(d.begin(), d.end(), cd(0.0, 0.0));
+        std::fill(e.begin(), e.end(), cd(0.0, 0.0));
+        for (int i = j + 1; i < n; ++i) {
+            const cd vi = v[i];
+            const cd *hc = &H(0, i), *yc = &Y(0, i);
+            for (int r = 0; r < n; ++r) {
+                d[r] += hc[r] * vi;
+                e[r] += yc[r] * vi;
             }
-            d *= tau;
-            e *= tau;
-            for (int i = j + 1; i < n; ++i) {
-                H(r, i) -= d * std::conj(v[i]);
-                Y(r, i) -= e * std::conj(v[i]);
+        }
+        for (int r = 0; r < n; ++r) {
+            d[r] *= tau;
+            e[r] *= tau;
+        }
+        for (int i = j + 1; i < n; ++i) {
+            const cd cv = std::conj(v[i]);
+            cd *hc = &H(0, i), *yc = &Y(0, i);
+            for (int r = 0; r < n; ++r) {
+                hc[r] -= d[r] * cv;
+                yc[r] -= e[r] * cv;
             }
         }
         H(j + 1, j) = beta;
