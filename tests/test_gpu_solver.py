@@ -484,3 +484,34 @@ def test_backward_matches_dense_derivatives(device, algorithm):
     _, gA_ref, gB_ref = OG.eig_grad_dense(Ad, Bd, sigma, k, g_ref, ra, A.indices, rb, B.indices)
     assert np.max(np.abs(gA - gA_ref)) <= 1e-8 * np.max(np.abs(gA_ref))
     assert np.max(np.abs(gB - gB_ref)) <= 1e-8 * np.max(np.abs(gB_ref))
+
+
+def test_workspace_reuse_gives_identical_solves(device):
+    # destroyed handles leave their workspace to the library's cache, where the
+    # next handle picks it up with whatever the previous solve wrote in it: the
+    # results must not depend on that (no read of unwritten workspace), and two
+    # live handles must not share a block
+    p = problems.config("d1", 3000)
+
+    def solve(**kw):
+        s, _, _ = gpu_solver(p, precision="fp64", tol=1e-10, max_iter=50, **kw)
+        st, _, _ = s.iterate()
+        out = s.schur()
+        s.close()
+        assert st == 0
+        return out["lam"], out["V"].cpu().numpy()
+
+    lam1, V1 = solve()
+    # scramble the cached blocks with a different workload and precision
+    q = problems.config("c4", 600)
+    s2, _, _ = gpu_solver(q, precision="mixed", tol=0.0, max_iter=3)
+    s2.iterate(3)
+    s2.close()
+    lam2, V2 = solve()
+    assert np.array_equal(lam1, lam2) and np.array_equal(V1, V2)
+    # a second handle alive while the first one solves
+    other, _, _ = gpu_solver(q, precision="fp64", tol=0.0, max_iter=2)
+    lam3, V3 = solve()
+    other.iterate(2)
+    other.close()
+    assert np.array_equal(lam1, lam3) and np.array_equal(V1, V3)
