@@ -312,6 +312,27 @@ def large_time_to_solution(G, torch, problems, n=4096000):
     return out
 
 
+def slow_time_to_solution(G, torch, problems, n=4096000):
+    """A slowly converging member of the family (coupling 4, diagonal T: about
+    25 iterations), where the complex64 phase covers part of the run:
+    complete solves to 1e-10, FP64 vs mixed (default switch at 1e-5, and at
+    1e-6)."""
+    p = problems.config("d2", n)
+    p.precond, p.sweeps, p.steps, p.inner = "diag", None, None, None
+    out = {"workload": f"diagonally dominant generalized pencil with coupling 4, n={p.n}, nnz={p.A.nnz}, "
+                       f"B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T=diag(A-sigma B)^-1"}
+    for key, prec, kw in (("fp64", "fp64", {}), ("mixed", "mixed", {}),
+                          ("mixed_switch_1e-6", "mixed", {"switch_tol": 1e-6})):
+        r, _ = timed_solve(G, torch, p, prec, reps=1, max_iter=300, **kw)
+        out[key] = r
+        log(f"[bench] d2/diag n={p.n} {key}: {r.get('s_per_solve', float('nan'))*1e3:.1f} ms, "
+            f"{r.get('iterations')} its ({r.get('fp64_iterations')} FP64), converged {r['converged']}")
+    if all(out[k]["converged"] for k in ("fp64", "mixed", "mixed_switch_1e-6")):
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+        out["speedup_mixed_switch_1e-6_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed_switch_1e-6"]["s_per_solve"]
+    return out
+
+
 def cpu_baseline(p):
     from oracle import gplhr_oracle as O
     t0 = time.perf_counter()
@@ -411,10 +432,12 @@ def main():
     if not args.no_next:
         nxt = next_rows(G, torch, problems, out_d["lam"])
 
-    large = None
+    large = large_slow = None
     if not args.no_large:
         log("[bench] building the n = 4096000 pencil for the large time-to-solution")
         large = large_time_to_solution(G, torch, problems)
+        torch.cuda.empty_cache()
+        large_slow = slow_time_to_solution(G, torch, problems)
         torch.cuda.empty_cache()
 
     named = {}
@@ -470,6 +493,7 @@ def main():
                             "update": stats_m["update_ms"], "host_small_step": stats_m["small_host_ms"]},
         "next_rows": nxt,
         "time_to_solution_4096000": large,
+        "time_to_solution_slow_4096000": large_slow,
         "named_workloads": named,
         "cpu_baseline": cpu,
     }
