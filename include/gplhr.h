@@ -159,7 +159,7 @@ typedef struct {
 } gplhr_options;
 
 /* Fill *opt with defaults: FP64, tol 1e-10, max_iter 500, arnoldi_m 1, thick P,
- * V0 NULL, seed 1, null stream, switch_tol 1e-5, stall_window 20, timing 0,
+ * V0 NULL, seed 1, null stream, switch_tol 1e-8, stall_window 3, timing 0,
  * proj_before_T 1, locking 0, m_max 20, algorithm SCHUR, no deflation. */
 void gplhr_default_options(gplhr_options *opt);
 

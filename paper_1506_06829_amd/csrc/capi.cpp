@@ -50,8 +50,8 @@ void gplhr_default_options(gplhr_options *opt) {
     opt->V0 = nullptr;
     opt->seed = 1;
     opt->hip_stream = nullptr;
-    opt->switch_tol = 1e-5;
-    opt->stall_window = 20;
+    opt->switch_tol = 1e-8;
+    opt->stall_window = 3;
     opt->timing = 0;
     opt->proj_before_T = 1;
     opt->locking = 0;

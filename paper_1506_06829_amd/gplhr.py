@@ -167,7 +167,7 @@ class Solver:
                  omega: float = 0.7, precision: str = "fp64", tol: float = 1e-10,
                  max_iter: int = 500, m: int = 1, p_mode: str = "thick",
                  V0: Optional[torch.Tensor] = None, seed: int = 1, timing: bool = False,
-                 switch_tol: float = 1e-5, stall_window: int = 20, stream=None,
+                 switch_tol: float = 1e-8, stall_window: int = 3, stream=None,
                  proj_before_T: bool = True, locking: bool = False, m_max: int = 20,
                  steps: int = 2, inner: str = "jacobi", algorithm: str = "schur",
                  deflate: Optional[tuple] = None):

@@ -36,7 +36,7 @@ def test_default_options():
     o = gplhr._Options()
     L.gplhr_default_options(ctypes.byref(o))
     assert o.precision == 0 and o.tol == 1e-10 and o.max_iter == 500 and o.arnoldi_m == 1
-    assert o.p_mode == 0 and o.switch_tol == 1e-5 and o.stall_window == 20
+    assert o.p_mode == 0 and o.switch_tol == 1e-8 and o.stall_window == 3
 
 
 def test_argument_errors_without_device_work():
