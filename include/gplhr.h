@@ -25,7 +25,10 @@
  *   gplhr_last_error(handle) (or gplhr_last_error(NULL) for errors raised
  *   before a handle exists).
  * - A handle is not thread-safe; separate handles are independent.  All
- *   device work of a handle runs on the stream given in gplhr_options.
+ *   device work of a handle runs on the stream given in gplhr_options, which
+ *   must outlive the handle.
+ * - Workspace released by gplhr_destroy stays cached by the library for
+ *   later handles (freeing device memory is slow) until the process ends.
  */
 #ifndef GPLHR_H
 #define GPLHR_H
@@ -261,7 +264,9 @@ typedef struct {
 
 gplhr_status gplhr_get_stats(gplhr_t h, gplhr_stats *out);
 
-/* Release the handle and all workspace it owns.  NULL is a no-op. */
+/* Release the handle and all workspace it owns (waits for the handle's
+ * stream; the device memory goes to the library's cache for later handles).
+ * NULL is a no-op. */
 void gplhr_destroy(gplhr_t h);
 
 /* Message of the last error on h (or of the last failed create when h is
