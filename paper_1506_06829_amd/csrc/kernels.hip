@@ -1043,6 +1043,7 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     // of R^{-1} goes to dinv).
     __shared__ double2 A[48 * 48];
     __shared__ double dsc[48];
+    __shared__ double rdiag[48];
     __shared__ double dinv[48];
     __shared__ int flag;
     const int tid = threadIdx.x;
@@ -1062,28 +1063,26 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         A[e].y *= dsc[i] * dsc[j];
     }
     __syncthreads();
+    // right-looking Cholesky with one barrier per column: every thread takes
+    // the pivot itself, and row j enters the trailing update scaled on the
+    // fly (the rows are scaled in place once the factorisation is done)
     const double tol = 64.0 * 2.220446049250313e-16;
+    auto pivot = [&](int j) {
+        const double piv = A[j + j * w].x;
+        // shifted factor below the tolerance; the second Cholesky-QR pass
+        // restores orthogonality
+        return (!(piv > tol) || !isfinite(piv)) ? tol : piv;
+    };
     for (int j = 0; j < w; ++j) {
-        if (tid == 0) {
-            double piv = A[j + j * w].x;
-            if (!(piv > tol) || !isfinite(piv)) {
-                piv = tol;   // shifted factor; the second Cholesky-QR pass restores orthogonality
-                flag += 1;
-            }
-            A[j + j * w] = make_double2(sqrt(piv), 0.0);
-        }
-        __syncthreads();
-        const double rjj = A[j + j * w].x;
-        for (int c = j + 1 + tid; c < w; c += 256) {
-            A[j + c * w].x /= rjj;
-            A[j + c * w].y /= rjj;
-        }
-        __syncthreads();
+        const double piv = A[j + j * w].x;
+        if (tid == 0 && (!(piv > tol) || !isfinite(piv))) flag += 1;
+        const double rs = 1.0 / sqrt(pivot(j));
         const int m = w - j - 1;
         for (int e = tid; e < m * m; e += 256) {
             const int ii = j + 1 + e % m, cc = j + 1 + e / m;
             if (ii <= cc) {
-                const double2 ri = A[j + ii * w], rc = A[j + cc * w];
+                const double2 a = A[j + ii * w], c = A[j + cc * w];
+                const double2 ri = make_double2(a.x * rs, a.y * rs), rc = make_double2(c.x * rs, c.y * rs);
                 double2 v = A[ii + cc * w];
                 v.x -= ri.x * rc.x + ri.y * rc.y;   // conj(ri) * rc
                 v.y -= ri.x * rc.y - ri.y * rc.x;
@@ -1092,26 +1091,37 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         }
         __syncthreads();
     }
-    // R^{-1}, row by row from the bottom: Rinv(i,j) = (delta_ij - sum_{l=i+1..j}
-    // R(i,l) Rinv(l,j)) / R(i,i); Rinv(i,j) (i<j) is kept at A[j + i*w].
-    for (int i = w - 1; i >= 0; --i) {
-        const double rii = A[i + i * w].x;
-        for (int j = i + tid; j < w; j += 256) {
-            if (j == i) {
-                dinv[i] = 1.0 / rii;
-            } else {
-                double2 s = make_double2(0.0, 0.0);
-                for (int l = i + 1; l <= j; ++l) {
-                    const double2 r = A[i + l * w];
-                    const double2 x = (l == j) ? make_double2(dinv[j], 0.0) : A[j + l * w];
-                    s.x += r.x * x.x - r.y * x.y;
-                    s.y += r.x * x.y + r.y * x.x;
-                }
-                A[j + i * w] = make_double2(-s.x / rii, -s.y / rii);
-            }
+    if (tid < w) rdiag[tid] = sqrt(pivot(tid));
+    __syncthreads();
+    for (int e = tid; e < w * w; e += 256) {
+        const int i = e % w, c = e / w;
+        if (i < c) {
+            const double r = 1.0 / rdiag[i];
+            A[e] = make_double2(A[e].x * r, A[e].y * r);
+        } else if (i == c) {
+            A[e] = make_double2(rdiag[i], 0.0);
+            dinv[i] = 1.0 / rdiag[i];
         }
-        __syncthreads();
     }
+    __syncthreads();
+    // R^{-1} by back substitution, one column per thread (no barriers):
+    // Rinv(i,j) = -(sum_{l=i+1..j} R(i,l) Rinv(l,j)) / R(i,i), kept at A[j + i*w]
+    if (tid < w) {
+        const int j = tid;
+        for (int i = j - 1; i >= 0; --i) {
+            const double2 r0 = A[i + j * w];
+            double2 s = make_double2(r0.x * dinv[j], r0.y * dinv[j]);
+#pragma unroll 4
+            for (int l = i + 1; l < j; ++l) {
+                const double2 r = A[i + l * w];
+                const double2 x = A[j + l * w];
+                s.x += r.x * x.x - r.y * x.y;
+                s.y += r.x * x.y + r.y * x.x;
+            }
+            A[j + i * w] = make_double2(-s.x * dinv[i], -s.y * dinv[i]);
+        }
+    }
+    __syncthreads();
     // X Rinv with Rinv = D R_s^{-1}
     for (int e = tid; e < w * w; e += 256) {
         const int i = e % w, j = e / w;
