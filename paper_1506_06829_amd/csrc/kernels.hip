@@ -1041,17 +1041,18 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     // A holds the scaled Gram; its upper triangle becomes R (A = R^H R) and
     // its strict lower triangle then receives R^{-1} transposed (the diagonal
     // of R^{-1} goes to dinv).
-    __shared__ double2 A[48 * 48];
+    __shared__ double2 A[48 * 49];   // leading dimension w + 1: a row of A spreads over the LDS banks
     __shared__ double dsc[48];
     __shared__ double rdiag[48];
     __shared__ double dinv[48];
     __shared__ int flag;
     const int tid = threadIdx.x;
+    const int lda = w + 1;
     if (tid == 0) flag = 0;
-    for (int e = tid; e < w * w; e += 256) A[e] = G[e];
+    for (int e = tid; e < w * w; e += 256) A[e % w + (e / w) * lda] = G[e];
     __syncthreads();
     if (tid < w) {
-        const double g = A[tid + tid * w].x;
+        const double g = A[tid + tid * lda].x;
         const bool ok = (g > 0.0) && isfinite(g);
         dsc[tid] = ok ? 1.0 / sqrt(g) : 1.0;
         if (!ok) atomicAdd(&flag, 1);
@@ -1059,8 +1060,8 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     __syncthreads();
     for (int e = tid; e < w * w; e += 256) {
         const int i = e % w, j = e / w;
-        A[e].x *= dsc[i] * dsc[j];
-        A[e].y *= dsc[i] * dsc[j];
+        A[i + j * lda].x *= dsc[i] * dsc[j];
+        A[i + j * lda].y *= dsc[i] * dsc[j];
     }
     __syncthreads();
     // right-looking Cholesky with one barrier per column: every thread takes
@@ -1068,26 +1069,29 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     // fly (the rows are scaled in place once the factorisation is done)
     const double tol = 64.0 * 2.220446049250313e-16;
     auto pivot = [&](int j) {
-        const double piv = A[j + j * w].x;
+        const double piv = A[j + j * lda].x;
         // shifted factor below the tolerance; the second Cholesky-QR pass
         // restores orthogonality
         return (!(piv > tol) || !isfinite(piv)) ? tol : piv;
     };
     for (int j = 0; j < w; ++j) {
-        const double piv = A[j + j * w].x;
+        const double piv = A[j + j * lda].x;
         if (tid == 0 && (!(piv > tol) || !isfinite(piv))) flag += 1;
         const double rs = 1.0 / sqrt(pivot(j));
         const int m = w - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int ii = j + 1 + e % m, cc = j + 1 + e / m;
-            if (ii <= cc) {
-                const double2 a = A[j + ii * w], c = A[j + cc * w];
-                const double2 ri = make_double2(a.x * rs, a.y * rs), rc = make_double2(c.x * rs, c.y * rs);
-                double2 v = A[ii + cc * w];
-                v.x -= ri.x * rc.x + ri.y * rc.y;   // conj(ri) * rc
-                v.y -= ri.x * rc.y - ri.y * rc.x;
-                A[ii + cc * w] = v;
-            }
+        // the upper triangle of the trailing block, entry e -> (a, b), a <= b
+        for (int e = tid; e < m * (m + 1) / 2; e += 256) {
+            int b = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+            if ((b + 1) * (b + 2) / 2 <= e) ++b;
+            if (b * (b + 1) / 2 > e) --b;
+            const int a = e - b * (b + 1) / 2;
+            const int ii = j + 1 + a, cc = j + 1 + b;
+            const double2 av = A[j + ii * lda], c = A[j + cc * lda];
+            const double2 ri = make_double2(av.x * rs, av.y * rs), rc = make_double2(c.x * rs, c.y * rs);
+            double2 v = A[ii + cc * lda];
+            v.x -= ri.x * rc.x + ri.y * rc.y;   // conj(ri) * rc
+            v.y -= ri.x * rc.y - ri.y * rc.x;
+            A[ii + cc * lda] = v;
         }
         __syncthreads();
     }
@@ -1095,30 +1099,42 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     __syncthreads();
     for (int e = tid; e < w * w; e += 256) {
         const int i = e % w, c = e / w;
+        double2 &ae = A[i + c * lda];
         if (i < c) {
             const double r = 1.0 / rdiag[i];
-            A[e] = make_double2(A[e].x * r, A[e].y * r);
+            ae = make_double2(ae.x * r, ae.y * r);
         } else if (i == c) {
-            A[e] = make_double2(rdiag[i], 0.0);
+            ae = make_double2(rdiag[i], 0.0);
             dinv[i] = 1.0 / rdiag[i];
         }
     }
     __syncthreads();
-    // R^{-1} by back substitution, one column per thread (no barriers):
-    // Rinv(i,j) = -(sum_{l=i+1..j} R(i,l) Rinv(l,j)) / R(i,i), kept at A[j + i*w]
-    if (tid < w) {
-        const int j = tid;
-        for (int i = j - 1; i >= 0; --i) {
-            const double2 r0 = A[i + j * w];
-            double2 s = make_double2(r0.x * dinv[j], r0.y * dinv[j]);
-#pragma unroll 4
-            for (int l = i + 1; l < j; ++l) {
-                const double2 r = A[i + l * w];
-                const double2 x = A[j + l * w];
+    // R^{-1} by back substitution, one column per group of 4 lanes of a
+    // wavefront (no barriers): Rinv(i,j) = -(sum_{l=i+1..j} R(i,l) Rinv(l,j))
+    // / R(i,i), kept at A[j + i*lda]; lane q of the group sums the terms with
+    // l = q mod 4 and the group adds its partial sums with lane swaps, so all
+    // four lanes hold (and store) the same value
+    {
+        const int j = tid >> 2, q = tid & 3;
+        // the four lanes of a group share j, so they take the same branch
+        // and the same trip counts
+        if (j < w) for (int i = j - 1; i >= 0; --i) {
+            double2 s = make_double2(0.0, 0.0);
+            if (q == 0) {
+                const double2 r0 = A[i + j * lda];
+                s = make_double2(r0.x * dinv[j], r0.y * dinv[j]);
+            }
+            for (int l = i + 1 + q; l < j; l += 4) {
+                const double2 r = A[i + l * lda];
+                const double2 x = A[j + l * lda];
                 s.x += r.x * x.x - r.y * x.y;
                 s.y += r.x * x.y + r.y * x.x;
             }
-            A[j + i * w] = make_double2(-s.x * dinv[i], -s.y * dinv[i]);
+            s.x += __shfl_xor(s.x, 1);
+            s.y += __shfl_xor(s.y, 1);
+            s.x += __shfl_xor(s.x, 2);
+            s.y += __shfl_xor(s.y, 2);
+            A[j + i * lda] = make_double2(-s.x * dinv[i], -s.y * dinv[i]);
         }
     }
     __syncthreads();
@@ -1129,12 +1145,12 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         if (i == j)
             v = make_double2(dinv[i], 0.0);
         else if (i < j)
-            v = A[j + i * w];
+            v = A[j + i * lda];
         Rinv[e] = make_double2(v.x * dsc[i], v.y * dsc[i]);
         if (Rout) {
             // G = D^{-1} R_s^H R_s D^{-1}: R = R_s D^{-1}
             double2 r = make_double2(0.0, 0.0);
-            if (i <= j) r = make_double2(A[i + j * w].x / dsc[j], A[i + j * w].y / dsc[j]);
+            if (i <= j) r = make_double2(A[i + j * lda].x / dsc[j], A[i + j * lda].y / dsc[j]);
             Rout[e] = r;
         }
     }
