@@ -407,6 +407,20 @@ def main():
     ri, ci = linear_sum_assignment(Cm)
     mixed_vs_fp64 = float(np.max(Cm[ri, ci] / np.abs(out_d["lam"][ci])))
 
+    # loss of orthogonality of the output bases (one more, untimed solve each)
+    def orth_loss(precision):
+        s = G.Solver(A, B, p.sigma, p.k, p.block, precond=p.precond, precision=precision, V0=V0,
+                     tol=1e-10, max_iter=400)
+        s.iterate()
+        o = s.schur()
+        s.close()
+        eye = torch.eye(p.k, dtype=torch.complex128, device="cuda")
+        V, Q = o["V"], o["Q"]
+        return {"V": float((V.conj().T @ V - eye).abs().max()), "Q": float((Q.conj().T @ Q - eye).abs().max())}
+    orth = {"mixed": orth_loss("mixed"), "fp64": orth_loss("fp64")}
+    log(f"[bench] max |V^H V - I|, |Q^H Q - I|: mixed {orth['mixed']['V']:.1e}, {orth['mixed']['Q']:.1e}; "
+        f"fp64 {orth['fp64']['V']:.1e}, {orth['fp64']['Q']:.1e}")
+
     # roofline of the dominant kernel class of the timed solves (HIP events)
     spmm_ms_per = stats_m["spmm_ms"] / max(1, stats_m["spmm_calls"])
     spmm_bytes_per = stats_m["spmm_bytes"] / max(1, stats_m["spmm_calls"])
@@ -448,12 +462,16 @@ def main():
     if not args.no_cpu:
         log("[bench] oracle CPU baseline (full FP64 solve of the same workload)")
         t_cpu, r_cpu = cpu_baseline(p)
-        Cc = np.abs(out_d["lam"][:, None] - r_cpu.lam[None, :p.k])
-        ri, ci = linear_sum_assignment(Cc)
+        def per_eig(lam):   # relative error of each eigenvalue against the oracle's
+            Cc = np.abs(lam[:, None] - r_cpu.lam[None, :p.k])
+            ri, ci = linear_sum_assignment(Cc)
+            return [float(x) for x in Cc[ri, ci] / np.abs(r_cpu.lam[ci])]
+        err_d, err_m = per_eig(out_d["lam"]), per_eig(out_m["lam"])
         cpu = {"value": t_cpu, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
                "sample": f"one complete FP64 oracle solve of the same workload "
                          f"({r_cpu.iterations} iterations, converged={r_cpu.converged}); "
-                         f"GPU-vs-oracle eigenvalue rel. diff {float(np.max(Cc[ri, ci] / np.abs(r_cpu.lam[ci]))):.2e}"}
+                         f"GPU-vs-oracle eigenvalue rel. diff {max(err_d):.2e} (FP64), {max(err_m):.2e} (mixed)",
+               "eig_rel_err_vs_oracle": {"fp64": err_d, "mixed": err_m}}
         log(f"[bench] oracle: {t_cpu:.2f} s")
 
     line = {
@@ -479,6 +497,7 @@ def main():
         "mixed": {"converged": st_m == 0, "max_rel_resid": res_m,
                   "eig_rel_diff_vs_fp64": mixed_vs_fp64},
         "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+        "orthogonality_loss": orth,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
                      "kernel": "spmm_kernel<float2,4,0> (CSR x 16-wide complex64 block, 160^3 upwind operator, "
