@@ -42,40 +42,54 @@ Mat matmul_hn(const Mat &A, const Mat &B) {
 }
 
 bool lu_solve(const Mat &Kin, const Mat &N, Mat &X) {
-    const int n = Kin.r;
+    const int n = Kin.r, nr = N.c;
     Mat K = Kin;
     X = N;
-    double kmax = 0.0;
-    for (const cd &v : K.a) kmax = std::max(kmax, std::abs(v));
+    double kmax2 = 0.0;
+    for (const cd &v : K.a) kmax2 = std::max(kmax2, std::norm(v));
+    const double kmax = std::sqrt(kmax2);
     if (!(kmax > 0.0) || !std::isfinite(kmax)) return false;
     const double tiny = kmax * n * DBL_EPSILON * 1e-3;
+    // right-looking elimination with the multipliers stored in place; every
+    // inner loop runs down a column (contiguous)
     for (int j = 0; j < n; ++j) {
         int p = j;
-        double best = std::abs(K(j, j));
+        double best = std::norm(K(j, j));
         for (int i = j + 1; i < n; ++i) {
-            double v = std::abs(K(i, j));
+            const double v = std::norm(K(i, j));
             if (v > best) { best = v; p = i; }
         }
-        if (!(best > tiny)) return false;
+        if (!(std::sqrt(best) > tiny)) return false;
         if (p != j) {
             for (int c = 0; c < n; ++c) std::swap(K(j, c), K(p, c));
-            for (int c = 0; c < X.c; ++c) std::swap(X(j, c), X(p, c));
+            for (int c = 0; c < nr; ++c) std::swap(X(j, c), X(p, c));
         }
         const cd inv = 1.0 / K(j, j);
-        for (int i = j + 1; i < n; ++i) {
-            const cd f = K(i, j) * inv;
-            if (f == cd(0.0, 0.0)) continue;
-            K(i, j) = 0.0;
-            for (int c = j + 1; c < n; ++c) K(i, c) -= f * K(j, c);
-            for (int c = 0; c < X.c; ++c) X(i, c) -= f * X(j, c);
+        cd *l = &K(0, j);
+        for (int i = j + 1; i < n; ++i) l[i] *= inv;
+        for (int c = j + 1; c < n; ++c) {
+            const cd u = K(j, c);
+            if (u == cd(0.0, 0.0)) continue;
+            cd *kc = &K(0, c);
+            for (int i = j + 1; i < n; ++i) kc[i] -= l[i] * u;
+        }
+        for (int c = 0; c < nr; ++c) {
+            const cd u = X(j, c);
+            if (u == cd(0.0, 0.0)) continue;
+            cd *xc = &X(0, c);
+            for (int i = j + 1; i < n; ++i) xc[i] -= l[i] * u;
         }
     }
-    for (int c = 0; c < X.c; ++c)
+    // back substitution, column by column of U
+    for (int c = 0; c < nr; ++c) {
+        cd *xc = &X(0, c);
         for (int i = n - 1; i >= 0; --i) {
-            cd acc = X(i, c);
-            for (int l = i + 1; l < n; ++l) acc -= K(i, l) * X(l, c);
-            X(i, c) = acc / K(i, i);
+            const cd v = xc[i] / K(i, i);
+            xc[i] = v;
+            const cd *ui = &K(0, i);
+            for (int r = 0; r < i; ++r) xc[r] -= ui[r] * v;
         }
+    }
     return true;
 }
 
