@@ -503,7 +503,7 @@ def main():
         "orthogonality_loss": orth,
         "roofline": {"bound": "hbm", "achieved": sp64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sp64["gbs"] / HBM_PEAK_GBS, "traffic": SPMM_C64_160_B16_TRAFFIC,
-                     "kernel": "spmm_kernel<float2,4,0> (CSR x 16-wide complex64 block, 160^3 upwind operator, "
+                     "kernel": "spmm_kernel<float2,4,0,8> (CSR x 16-wide complex64 block, 160^3 upwind operator, "
                                f"plane-slab row schedule, plane {sp64['plane']})",
                      "bytes_per_launch": sp64["bytes"], "ms_per_launch": sp64["ms"]},
         "spmm": {"c64_gbs": sp64["gbs"], "c128_gbs": sp128["gbs"], "c64_ms": sp64["ms"],

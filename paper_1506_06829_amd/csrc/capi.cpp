@@ -243,7 +243,7 @@ gplhr_status gplhr_eig_backward(gplhr_t h, const double *grad_lambda, void *grad
             GPLHR_HIP_CHECK(hipMalloc((void **)&BX, sizeof(double2) * n * k));
             cl.p.push_back(BX);
             gplhr::launch_spmm<double2>(st, n, c.b_rp, c.b_ci, c.b_val, X, k, BX, k, k, 0, nullptr, 0,
-                                        nullptr, c.b_plane);
+                                        nullptr, c.b_plane, c.b_nnz);
             bx = BX;
         }
         c.gram<double2>(Y, k, k, bx, k, k, bsc, c.g0);
@@ -319,11 +319,11 @@ const char *gplhr_last_error(gplhr_t h) {
     return g_last_error.c_str();
 }
 
-gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
-                        const void *val, const void *X, int ldx, void *Y, int ldy, int b,
-                        int plane, void *hip_stream) {
+gplhr_status gplhr_spmm(int dtype, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                        const int32_t *col_idx, const void *val, const void *X, int ldx, void *Y,
+                        int ldy, int b, int plane, void *hip_stream) {
     return guard(nullptr, [&]() {
-        if (n < 0 || b < 1 || b > 64 || ldx < b || ldy < b || (dtype != 0 && dtype != 1) ||
+        if (n < 0 || nnz < 0 || b < 1 || b > 64 || ldx < b || ldy < b || (dtype != 0 && dtype != 1) ||
             plane < 0 || (plane > 0 && (n % plane != 0 || plane % 8 != 0)))
             throw gplhr::Error(-1, "gplhr_spmm: bad arguments");
         if (n == 0) return 0;
@@ -333,12 +333,12 @@ gplhr_status gplhr_spmm(int dtype, int64_t n, const int32_t *row_ptr, const int3
             gplhr::launch_spmm<double2>(st, n, row_ptr, col_idx, static_cast<const double2 *>(val),
                                         static_cast<const double2 *>(X), ldx,
                                         static_cast<double2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
-                                        plane);
+                                        plane, nnz);
         else
             gplhr::launch_spmm<float2>(st, n, row_ptr, col_idx, static_cast<const float2 *>(val),
                                        static_cast<const float2 *>(X), ldx,
                                        static_cast<float2 *>(Y), ldy, b, 0, nullptr, 0, nullptr,
-                                       plane);
+                                       plane, nnz);
         return 0;
     });
 }

@@ -164,7 +164,7 @@ template <typename T>
 void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int wc, int mode, const T *Rhs, int ldr) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, c_plane);
+    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, c_plane, c_nnz);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
@@ -175,7 +175,7 @@ template <typename T>
 void Ctx::spmm_b(const T *X, int ldx, T *Y, int ldy, int wc) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, wc, 0, nullptr, 0, nullptr, b_plane);
+    launch_spmm<T>(st, n, b_rp, b_ci, w.bval, X, ldx, Y, ldy, wc, 0, nullptr, 0, nullptr, b_plane, b_nnz);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)b_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) + 2.0 * n * wc * sizeof(T);

@@ -39,11 +39,13 @@ void pinned_free(void *p, size_t bytes);
 // Y = C X (mode 0) or, for the damped Jacobi sweep, Y = X + dw .* (Rhs - C X)
 // (mode 1), where dw holds omega / C(i,i) per row.  plane > 0 runs the rows
 // in the plane-slab order (plane rows per plane; must divide n and be a
-// multiple of 8), 0 in natural order; the result is the same.
+// multiple of 8), 0 in natural order; the result is the same.  nnz (the
+// stored entries, rp[n]) sets how many entries of a row are gathered at once;
+// any value >= 0 gives the same result.
 template <typename T>
 void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, const T *val,
                  const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
-                 const T *dw, int plane);
+                 const T *dw, int plane, int64_t nnz);
 // Plane for launch_spmm: the pattern's bandwidth max |j - i| when it splits
 // n into at least four planes of at least 512 rows (a multiple of 8), else 0.
 // Synchronous.

@@ -123,11 +123,10 @@ struct SpmmArgs {
     int sperx;      // rows per XCD: n / 8
 };
 
-constexpr int SPMM_BATCH = 8;
-
 // MODE 0: Y = C X; MODE 1: the damped Jacobi sweep (compile-time, so the plain
-// product carries no epilogue registers)
-template <typename T, int CPL, int MODE>
+// product carries no epilogue registers).  BATCH entries of a row have their
+// block-row gathers in flight together.
+template <typename T, int CPL, int MODE, int BATCH>
 __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     int blk = blockIdx.x;
     if (a.per_xcd > 0) {
@@ -162,18 +161,18 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     const T *__restrict__ Xc = a.X + c0;
     // whole batches of the row's index/value stream are in flight before the
     // dependent block-row gathers are issued
-    for (int p = p0; p < p1; p += SPMM_BATCH) {
-        int j[SPMM_BATCH];
-        T v[SPMM_BATCH];
+    for (int p = p0; p < p1; p += BATCH) {
+        int j[BATCH];
+        T v[BATCH];
 #pragma unroll
-        for (int u = 0; u < SPMM_BATCH; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
             const bool ok = p + u < p1;
             j[u] = ok ? a.ci[p + u] : -1;
             v[u] = ok ? a.val[p + u] : czero<T>();
         }
-        T x[SPMM_BATCH][CPL];
+        T x[BATCH][CPL];
 #pragma unroll
-        for (int u = 0; u < SPMM_BATCH; ++u) {
+        for (int u = 0; u < BATCH; ++u) {
             if (j[u] >= 0) {
                 load_vec<T, CPL>(Xc + (int64_t)j[u] * a.ldx, x[u]);
             } else {
@@ -182,7 +181,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < SPMM_BATCH; ++u)
+        for (int u = 0; u < BATCH; ++u)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cfma(acc[c], v[u], x[u][c]);
     }
@@ -209,10 +208,41 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 // plane after plane: the three planes of one slab that a block touches fit
 // in that XCD's L2, and every block row is fetched about once (160^3 operator,
 // 16 complex64 columns: 1.96 -> 0.93 GB read per product).
+//
+// Batch length.  A row's entries are taken BATCH at a time: their indices and
+// values first, then all their block-row gathers, so a row of at most BATCH
+// entries costs one round of dependent latencies.  BATCH follows the typical
+// row length (nnz / n): 8, 12 or 17 slots.  17 is the most the complex128
+// kernel with two columns per lane keeps within 256 VGPRs (225, two waves per
+// SIMD); 20 slots overflow into AGPRs at one wave per SIMD and run slower.
+// Measured at n = 262144, 17 random entries per row, 10 complex128 columns:
+// 176 us with 8 slots, 166 us with 12, 153 us with 17; the 7-point 160^3
+// operator (16 complex64 columns) keeps 8 (431 us; 17 slots: 564 us).
+template <typename T, int MODE, int BATCH>
+static void spmm_go(hipStream_t st, const SpmmArgs<T> &a, int cpl, int grid) {
+    if constexpr (sizeof(T) == 8) {
+        if (cpl == 4) {
+            hipLaunchKernelGGL((spmm_kernel<T, 4, MODE, BATCH>), dim3(grid), dim3(256), 0, st, a);
+            return;
+        }
+    }
+    if (cpl == 2)
+        hipLaunchKernelGGL((spmm_kernel<T, 2, MODE, BATCH>), dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((spmm_kernel<T, 1, MODE, BATCH>), dim3(grid), dim3(256), 0, st, a);
+}
+
+template <typename T, int MODE>
+static void spmm_batch(hipStream_t st, const SpmmArgs<T> &a, int cpl, int grid, int row_len) {
+    if (row_len <= 8) spmm_go<T, MODE, 8>(st, a, cpl, grid);
+    else if (row_len <= 12) spmm_go<T, MODE, 12>(st, a, cpl, grid);
+    else spmm_go<T, MODE, 17>(st, a, cpl, grid);
+}
+
 template <typename T>
 void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci, const T *val,
                  const T *X, int ldx, T *Y, int ldy, int b, int mode, const T *Rhs, int ldr,
-                 const T *dw, int plane) {
+                 const T *dw, int plane, int64_t nnz) {
     if (n <= 0) return;
     if (plane < 0 || (plane > 0 && (n % plane != 0 || plane % 8 != 0)))
         throw Error(-1, "spmm: the plane must divide n and be a multiple of 8");
@@ -244,30 +274,20 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
         a.ss = plane / 8;
         a.sperx = (int)(n / 8);
     }
-    if (mode == 0) {
-        if (cpl == 4)
-            hipLaunchKernelGGL((spmm_kernel<T, 4, 0>), dim3(grid), dim3(256), 0, st, a);
-        else if (cpl == 2)
-            hipLaunchKernelGGL((spmm_kernel<T, 2, 0>), dim3(grid), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((spmm_kernel<T, 1, 0>), dim3(grid), dim3(256), 0, st, a);
-    } else {
-        if (cpl == 4)
-            hipLaunchKernelGGL((spmm_kernel<T, 4, 1>), dim3(grid), dim3(256), 0, st, a);
-        else if (cpl == 2)
-            hipLaunchKernelGGL((spmm_kernel<T, 2, 1>), dim3(grid), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((spmm_kernel<T, 1, 1>), dim3(grid), dim3(256), 0, st, a);
-    }
+    // typical entries per row, rounded up
+    const int64_t row_len = nnz > 0 ? (nnz + n - 1) / n : 0;
+    const int rl = (int)std::min<int64_t>(row_len, 1 << 20);
+    if (mode == 0) spmm_batch<T, 0>(st, a, cpl, grid, rl);
+    else spmm_batch<T, 1>(st, a, cpl, grid, rl);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
 template void launch_spmm<double2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
                                    const double2 *, const double2 *, int, double2 *, int, int,
-                                   int, const double2 *, int, const double2 *, int);
+                                   int, const double2 *, int, const double2 *, int, int64_t);
 template void launch_spmm<float2>(hipStream_t, int64_t, const int32_t *, const int32_t *,
                                   const float2 *, const float2 *, int, float2 *, int, int, int,
-                                  const float2 *, int, const float2 *, int);
+                                  const float2 *, int, const float2 *, int, int64_t);
 
 // Largest |j - i| over the stored entries (columns sorted within each row:
 // the first and the last entry of a row bound it).

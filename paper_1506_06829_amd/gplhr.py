@@ -103,7 +103,7 @@ def lib():
     L.gplhr_destroy.restype = None
     L.gplhr_last_error.argtypes = [vp]
     L.gplhr_last_error.restype = ctypes.c_char_p
-    L.gplhr_spmm.argtypes = [i32, i64, vp, vp, vp, vp, i32, vp, i32, i32, i32, vp]
+    L.gplhr_spmm.argtypes = [i32, i64, i64, vp, vp, vp, vp, i32, vp, i32, i32, i32, vp]
     L.gplhr_spmm.restype = i32
     L.gplhr_csr_plane.argtypes = [i64, vp, vp, ctypes.POINTER(i32), vp]
     L.gplhr_csr_plane.restype = i32
@@ -292,7 +292,7 @@ def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
     b = X.shape[1]
     if Y is None:
         Y = torch.empty((A.n, b), dtype=X.dtype, device=X.device)
-    _check(lib().gplhr_spmm(dtype, A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
+    _check(lib().gplhr_spmm(dtype, A.n, A.nnz, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
                             X.stride(0), _ptr(Y), Y.stride(0), b, int(plane), _stream_ptr()))
     return Y
 

@@ -49,12 +49,14 @@ def test_argument_errors_without_device_work():
     assert b"A must be" in L.gplhr_last_error(None)
     assert L.gplhr_create(None, None, 0.0, 0.0, 1, 1, None, None, None) == -1
     # bad block widths for the single-kernel entry points
-    assert L.gplhr_spmm(0, 10, None, None, None, None, 4, None, 4, 0, 0, None) == -1
-    assert L.gplhr_spmm(0, 10, None, None, None, None, 2, None, 4, 4, 0, None) == -1
+    assert L.gplhr_spmm(0, 10, 0, None, None, None, None, 4, None, 4, 0, 0, None) == -1
+    assert L.gplhr_spmm(0, 10, 0, None, None, None, None, 2, None, 4, 4, 0, None) == -1
     # the plane must divide n and be a multiple of 8
-    assert L.gplhr_spmm(0, 48, None, None, None, None, 4, None, 4, 4, 12, None) == -1
-    assert L.gplhr_spmm(0, 40, None, None, None, None, 4, None, 4, 4, 16, None) == -1
-    assert L.gplhr_spmm(0, 40, None, None, None, None, 4, None, 4, 4, -8, None) == -1
+    assert L.gplhr_spmm(0, 48, 0, None, None, None, None, 4, None, 4, 4, 12, None) == -1
+    assert L.gplhr_spmm(0, 40, 0, None, None, None, None, 4, None, 4, 4, 16, None) == -1
+    assert L.gplhr_spmm(0, 40, 0, None, None, None, None, 4, None, 4, 4, -8, None) == -1
+    # negative nnz
+    assert L.gplhr_spmm(0, 10, -1, None, None, None, None, 4, None, 4, 4, 0, None) == -1
     assert L.gplhr_csr_plane(10, None, None, None, None) == -1
     assert L.gplhr_gram(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
     for wx, wy in [(0, 4), (129, 4), (4, 0), (4, 49)]:

@@ -51,6 +51,38 @@ def test_spmm_matches_definition(device, b, dtype):
         assert np.array_equal(Y, Y2)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("b", [2, 10, 16])
+def test_spmm_batch_lengths(device, dtype, b):
+    # nnz only picks how many entries of a row are gathered at once (8, 12 or
+    # 17 by nnz / n): every choice accumulates a row in the same order, so the
+    # products are bitwise equal, and equal the definition; rows of up to 79
+    # entries take several batches of each length
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(100 + b)
+    csr = _rand_csr(777, rng, max_row=80, empty_every=5)
+    n = csr.n
+    A = G.DeviceCsr.from_host(csr)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    X = torch.as_tensor(_block(rng, n, b)).to(device, tdt)
+    val = A.val.to(tdt)
+    outs = []
+    for hint in (0, 8 * n, 10 * n, 12 * n, 13 * n, 17 * n, 100 * n):
+        Y = torch.empty_like(X)
+        G._check(G.lib().gplhr_spmm(0 if dtype == "c128" else 1, n, hint, G._ptr(A.row_ptr),
+                                    G._ptr(A.col_idx), G._ptr(val), G._ptr(X), b, G._ptr(Y), b, b,
+                                    0, G._stream_ptr()))
+        outs.append(Y.cpu().numpy())
+    for Y in outs[1:]:
+        assert np.array_equal(Y, outs[0])
+    Xh = X.cpu().numpy()
+    ref = csr.to_scipy().astype(Xh.dtype) @ Xh
+    scale = np.abs(csr.to_scipy()) @ np.abs(Xh) + 1e-300
+    tol = 1e-14 if dtype == "c128" else 2e-6
+    assert np.max(np.abs(outs[0] - ref) / scale) < tol
+
+
 def test_spmm_empty_matrix_rows(device):
     import torch
     from paper_1506_06829_amd import gplhr as G
