@@ -311,6 +311,25 @@ gplhr_status gplhr_csr_plane(int64_t n, const int32_t *row_ptr, const int32_t *c
 gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
                         const void *Y, int ldy, int by, void *G, void *hip_stream);
 
+/* Y = T R for the damped Jacobi preconditioner on C: T approximates C^{-1}
+ * for C = A - sigma B, as Section 4 asks of the preconditioner that Algorithm
+ * 2 applies in its steps 8 and 15.  From w_0 = 0, sweeps steps of
+ * w <- w + omega diag(C)^{-1} (R - C w) (the first one is omega diag(C)^{-1} R,
+ * so sweeps - 1 sparse products); the same kernels as the solver's
+ * GPLHR_PRECOND_JACOBI.  C is a device CSR (n, nnz, row_ptr, col_idx with
+ * sorted columns) with complex128 values val; R (ldr >= b) and Y (ldy >= b)
+ * are row-major device blocks of dtype 0 (complex128) or 1 (complex64: the
+ * values and omega / diag(C) are rounded to complex64 and the products
+ * accumulate in FP32, as in the solver's complex64 phase).  Y must not
+ * overlap R.  plane as for gplhr_spmm.  Works in scratch blocks from the
+ * library's device cache and waits for the result before returning.
+ * Returns ARG for a bad size, b outside 1..64, sweeps outside 1..64,
+ * omega <= 0 or non-finite, a bad plane, or a zero or missing diagonal entry. */
+gplhr_status gplhr_jacobi(int dtype, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, const void *val, double omega, int sweeps,
+                          const void *R, int ldr, void *Y, int ldy, int b, int plane,
+                          void *hip_stream);
+
 /* Y(:, 0:wy) = beta Y(:, 0:wy) + X(:, 0:wx) M, the row-local block update
  * behind every basis change of Algorithm 2: the new V, P and Q from the trial
  * and test bases and the ordered Schur vectors (Section 3.5), the projections

@@ -375,6 +375,83 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Y = T R with T the damped Jacobi iteration on C w = R from w_0 = 0:
+// w_1 = dw .* R, w_{t+1} = w_t + dw .* (R - C w_t), dw = omega / diag(C).
+// The same kernel sequence as the solver's preconditioner application.
+template <typename T>
+void jacobi_apply(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                  const T *val, const T *dw, int sweeps, const T *R, int ldr, T *Y, int ldy, int b,
+                  int plane) {
+    if (sweeps == 1) {
+        gplhr::launch_scale_rows<T>(st, n, b, R, ldr, dw, Y, ldy);
+        return;
+    }
+    T *J[2] = {static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st)), nullptr};
+    if (sweeps > 2) J[1] = static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st));
+    gplhr::launch_scale_rows<T>(st, n, b, R, ldr, dw, J[0], b);
+    int cur = 0;
+    for (int t = 1; t < sweeps; ++t) {
+        const bool last = (t == sweeps - 1);
+        T *o = last ? Y : J[1 - cur];
+        gplhr::launch_spmm<T>(st, n, rp, ci, val, J[cur], b, o, last ? ldy : b, b, 1, R, ldr, dw,
+                              plane, nnz);
+        cur = 1 - cur;
+    }
+    gplhr::dev_free(J[0], st);
+    if (J[1]) gplhr::dev_free(J[1], st);
+}
+}  // namespace
+
+extern "C" {
+
+gplhr_status gplhr_jacobi(int dtype, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, const void *val, double omega, int sweeps,
+                          const void *R, int ldr, void *Y, int ldy, int b, int plane,
+                          void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 0 || nnz < 0 || nnz > INT32_MAX || b < 1 || b > 64 || ldr < b || ldy < b ||
+            sweeps < 1 || sweeps > 64 || !(omega > 0.0) || !std::isfinite(omega) ||
+            (dtype != 0 && dtype != 1) || plane < 0 ||
+            (plane > 0 && (n % plane != 0 || plane % 8 != 0)))
+            throw gplhr::Error(-1, "gplhr_jacobi: bad arguments");
+        if (n == 0) return 0;
+        if (!row_ptr || !col_idx || !val || !R || !Y) throw gplhr::Error(-1, "gplhr_jacobi: null pointer");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const double2 *v = static_cast<const double2 *>(val);
+        double2 *dg = static_cast<double2 *>(gplhr::dev_alloc(sizeof(double2) * n, st));
+        const int64_t zeros = gplhr::extract_diag(st, n, row_ptr, col_idx, v, dg);
+        if (zeros) {
+            gplhr::dev_free(dg, st);
+            throw gplhr::Error(-1, "gplhr_jacobi: diag(C) has " + std::to_string(zeros) + " zero entries");
+        }
+        double2 *dw = static_cast<double2 *>(gplhr::dev_alloc(sizeof(double2) * n, st));
+        gplhr::launch_recip_scaled(st, n, dg, make_double2(omega, 0.0), dw);
+        if (dtype == 0) {
+            jacobi_apply<double2>(st, n, nnz, row_ptr, col_idx, v, dw, sweeps,
+                                  static_cast<const double2 *>(R), ldr, static_cast<double2 *>(Y),
+                                  ldy, b, plane);
+        } else {
+            // complex64 copies of the values and of omega / diag(C), as in the
+            // solver's complex64 phase
+            float2 *v32 = nnz ? static_cast<float2 *>(gplhr::dev_alloc(sizeof(float2) * nnz, st)) : nullptr;
+            float2 *dw32 = static_cast<float2 *>(gplhr::dev_alloc(sizeof(float2) * n, st));
+            if (nnz) gplhr::launch_c128_to_c64_flat(st, nnz, v, v32);
+            gplhr::launch_c128_to_c64_flat(st, n, dw, dw32);
+            jacobi_apply<float2>(st, n, nnz, row_ptr, col_idx, v32, dw32, sweeps,
+                                 static_cast<const float2 *>(R), ldr, static_cast<float2 *>(Y),
+                                 ldy, b, plane);
+            if (v32) gplhr::dev_free(v32, st);
+            gplhr::dev_free(dw32, st);
+        }
+        gplhr::dev_free(dg, st);
+        gplhr::dev_free(dw, st);
+        return 0;
+    });
+}
+
 gplhr_status gplhr_block_update(int dtype, int64_t n, const void *X, int ldx, int wx,
                                 const void *M, int ldm, void *Y, int ldy, int wy,
                                 double beta_re, double beta_im, void *hip_stream) {

@@ -68,7 +68,7 @@ class _Stats(ctypes.Structure):
 EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_schur",
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
-           "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram",
+           "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram", "gplhr_jacobi",
            "gplhr_block_update"]
 
 
@@ -105,6 +105,9 @@ def lib():
     L.gplhr_last_error.restype = ctypes.c_char_p
     L.gplhr_spmm.argtypes = [i32, i64, i64, vp, vp, vp, vp, i32, vp, i32, i32, i32, vp]
     L.gplhr_spmm.restype = i32
+    L.gplhr_jacobi.argtypes = [i32, i64, i64, vp, vp, vp, ctypes.c_double, i32, vp, i32, vp, i32,
+                               i32, i32, vp]
+    L.gplhr_jacobi.restype = i32
     L.gplhr_csr_plane.argtypes = [i64, vp, vp, ctypes.POINTER(i32), vp]
     L.gplhr_csr_plane.restype = i32
     L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
@@ -294,6 +297,20 @@ def spmm(A: DeviceCsr, X: torch.Tensor, Y: Optional[torch.Tensor] = None,
         Y = torch.empty((A.n, b), dtype=X.dtype, device=X.device)
     _check(lib().gplhr_spmm(dtype, A.n, A.nnz, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(v), _ptr(X),
                             X.stride(0), _ptr(Y), Y.stride(0), b, int(plane), _stream_ptr()))
+    return Y
+
+
+def jacobi(A: DeviceCsr, R: torch.Tensor, omega: float = 0.7, sweeps: int = 3,
+           plane: int = 0) -> torch.Tensor:
+    """Y = T R for ``sweeps`` damped Jacobi steps on A (complex128 values)
+    from zero, with the library's kernels; R complex128 or complex64."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[R.dtype]
+    assert R.dim() == 2 and R.stride(1) == 1 and A.val.dtype == torch.complex128
+    b = R.shape[1]
+    Y = torch.empty((A.n, b), dtype=R.dtype, device=R.device)
+    _check(lib().gplhr_jacobi(dtype, A.n, A.nnz, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(A.val),
+                              float(omega), int(sweeps), _ptr(R), R.stride(0), _ptr(Y), b, b,
+                              int(plane), _stream_ptr()))
     return Y
 
 

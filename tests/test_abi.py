@@ -18,7 +18,7 @@ def test_header_declares_the_boundary():
     syms = declared_symbols()
     for s in ["gplhr_create", "gplhr_iterate", "gplhr_get_schur", "gplhr_eig_backward",
               "gplhr_destroy", "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane",
-              "gplhr_gram", "gplhr_block_update"]:
+              "gplhr_gram", "gplhr_block_update", "gplhr_jacobi"]:
         assert s in syms
 
 
@@ -57,6 +57,16 @@ def test_argument_errors_without_device_work():
     assert L.gplhr_spmm(0, 40, 0, None, None, None, None, 4, None, 4, 4, -8, None) == -1
     # negative nnz
     assert L.gplhr_spmm(0, 10, -1, None, None, None, None, 4, None, 4, 4, 0, None) == -1
+    # Jacobi: sweeps, omega, widths, nnz, plane
+    for args in [(0, 10, 30, 0.7, 0, 4, 4, 4, 0), (0, 10, 30, 0.7, 65, 4, 4, 4, 0),
+                 (0, 10, 30, 0.0, 3, 4, 4, 4, 0), (0, 10, 30, float("nan"), 3, 4, 4, 4, 0),
+                 (0, 10, 30, 0.7, 3, 2, 4, 4, 0), (0, 10, 30, 0.7, 3, 4, 4, 65, 0),
+                 (0, 10, -1, 0.7, 3, 4, 4, 4, 0), (2, 10, 30, 0.7, 3, 4, 4, 4, 0),
+                 (0, 48, 30, 0.7, 3, 4, 4, 4, 12)]:
+        dt, n, nnz, om, sw, ldr, ldy, b, plane = args
+        assert L.gplhr_jacobi(dt, n, nnz, None, None, None, ctypes.c_double(om), sw, None, ldr,
+                              None, ldy, b, plane, None) == -1
+    assert b"gplhr_jacobi" in L.gplhr_last_error(None)
     assert L.gplhr_csr_plane(10, None, None, None, None) == -1
     assert L.gplhr_gram(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
     for wx, wy in [(0, 4), (129, 4), (4, 0), (4, 49)]:

@@ -83,6 +83,51 @@ def test_spmm_batch_lengths(device, dtype, b):
     assert np.max(np.abs(outs[0] - ref) / scale) < tol
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("sweeps", [1, 2, 3, 4])
+def test_jacobi_matches_oracle(device, dtype, sweeps):
+    # the preconditioner T (damped Jacobi from zero) against the oracle's, on
+    # a 3-D upwind stencil (7 entries per row, plane schedule), the shifted
+    # diagonally dominant pencil (17 per row) and a ragged random pattern with
+    # a dominant diagonal (rows of 1..40 entries)
+    import torch
+    from oracle import gplhr_oracle as O
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(10 + sweeps)
+    sten = problems.convection_diffusion(16, (20.0, 10.0, 5.0))
+    Ad, Bd = problems.diag_dominant_pencil(3000, seed=2)
+    sig = 1500.0 + 0.3j
+    Cd = Ad.to_scipy() - sig * Bd.to_scipy()
+    Cr = _rand_csr(999, rng).to_scipy()
+    Cr = Cr + sp.diags(3.0 * np.abs(Cr).sum(axis=1).A1 + 1.0)
+    for C, plane in [(sten.to_scipy(), 256), (sp.csr_matrix(Cd), 0), (sp.csr_matrix(Cr), 0)]:
+        C.sort_indices()
+        csr = problems.csr_from_scipy(C)
+        A = G.DeviceCsr.from_host(csr)
+        T = O.make_preconditioner(C, "jacobi", sweeps=sweeps, omega=0.7)
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        for b in (1, 10, 16):
+            R = _block(rng, csr.n, b)
+            Rd = torch.as_tensor(R).to(device, tdt)
+            Y = G.jacobi(A, Rd, omega=0.7, sweeps=sweeps, plane=plane).cpu().numpy()
+            ref = T(Rd.cpu().numpy().astype(np.complex128))
+            tol = 1e-13 if dtype == "c128" else 5e-6
+            assert np.max(np.abs(Y - ref)) < tol * np.max(np.abs(ref)), (C.shape, b)
+            if plane:
+                Y0 = G.jacobi(A, Rd, omega=0.7, sweeps=sweeps).cpu().numpy()
+                assert np.array_equal(Y, Y0)
+
+
+def test_jacobi_zero_diagonal(device):
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    C = sp.csr_matrix(np.array([[2.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 2.0]], dtype=complex))
+    A = G.DeviceCsr.from_host(problems.csr_from_scipy(C))
+    R = torch.ones((3, 2), dtype=torch.complex128, device=device)
+    with pytest.raises(Exception, match="zero entries"):
+        G.jacobi(A, R)
+
+
 def test_spmm_empty_matrix_rows(device):
     import torch
     from paper_1506_06829_amd import gplhr as G
