@@ -101,18 +101,39 @@ struct Rot {
 
 static Rot make_rot(const cd &f, const cd &g) {
     Rot R;
-    if (g == cd(0.0, 0.0)) {
+    const double sf = abs1(f), sg = abs1(g);
+    if (sg == 0.0) {
         R.c = 1.0;
         R.s = 0.0;
-    } else if (f == cd(0.0, 0.0)) {
-        R.c = 0.0;
-        R.s = std::conj(g) / std::abs(g);
-    } else {
-        const double af = std::abs(f), ag = std::abs(g);
-        const double nrm = std::hypot(af, ag);
-        R.c = af / nrm;
-        R.s = (f / af) * std::conj(g) / nrm;
+        return R;
     }
+    const double sc = std::max(sf, sg);
+    if (!(sc > 1e-290 && sc < 1e290)) {
+        // extreme magnitudes (or NaN): the library moduli, which scale inside
+        if (sf == 0.0) {
+            R.c = 0.0;
+            R.s = std::conj(g) / std::abs(g);
+        } else {
+            const double af = std::abs(f), nrm = std::hypot(af, std::abs(g));
+            R.c = af / nrm;
+            R.s = (f / af) * std::conj(g) / nrm;
+        }
+        return R;
+    }
+    // scaled by the larger 1-norm, the squares neither overflow nor underflow
+    // to zero; |f| and sqrt(|f|^2 + |g|^2) then take two square roots
+    const double inv = 1.0 / sc;
+    const cd fs = f * inv, gs = g * inv;
+    const double f2 = std::norm(fs), g2 = std::norm(gs);
+    if (f2 == 0.0) {
+        // f = 0, or below 1e-154 |g|: the rotation that swaps up g
+        R.c = 0.0;
+        R.s = std::conj(gs) / std::sqrt(g2);
+        return R;
+    }
+    const double af = std::sqrt(f2), nrm = std::sqrt(f2 + g2);
+    R.c = af / nrm;
+    R.s = fs * std::conj(gs) / (af * nrm);
     return R;
 }
 
