@@ -367,8 +367,11 @@ template <> struct RealOf<float2> { using R = float; };
 
 constexpr int GM_PF = 4;   // K steps in flight per wave
 
-template <typename T, int MTC, int NTC, int PF = GM_PF>
-__global__ __launch_bounds__(256) void gram_mfma_kernel(GramMArgs<T> a) {
+// OCC: waves per SIMD the register allocation must leave room for (1: the
+// compiler's choice; 2: at most 256 VGPRs + AGPRs per lane).
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, 8)))
+void gram_mfma_kernel(GramMArgs<T> a) {
     using R = typename RealOf<T>::R;
     __shared__ double red[2 * MTC * NTC * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -557,7 +560,7 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T, int MTC, int NTC, int PF = GM_PF>
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
 static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
                                 int ldo, int nblk_want) {
     a.G = (a.NT + NTC - 1) / NTC;
@@ -574,7 +577,7 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
     // no block starts past the last row
     a.nblk = (int)((a.n + a.rows_per_blk - 1) / a.rows_per_blk);
-    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF>), dim3(a.nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(a.bx * a.by), dim3(256), 0, st, a.part,
                        a.nblk, a.bx, out, ldo);
@@ -596,6 +599,13 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
     // flight measured on n = 262144 and 4096000: narrow X (at most 2 M tiles)
     // takes 512 blocks, wider shapes 256 (one block per CU at their VGPR use)
     const int nb = (a.MT <= 2) ? 512 : 256;
+    // Tall blocks (from 2^20 rows): the tile sets that hold one wave per SIMD
+    // at their own register use are built for two (two K steps in flight
+    // instead of four) and launched as 512 blocks, two per CU.  At 4096000
+    // rows: 64 x 64 3326 -> 3030 us, 48 x 48 2021 -> 1811 us, 32 x 32
+    // 1043 -> 984 us, 64 x 16 1129 -> 1055 us; at 262144 rows 48 x 48 went
+    // the other way (180 -> 200 us), hence the row threshold.
+    const bool tall = a.n >= ((int64_t)1 << 20);
     if (a.NT <= 2) {
         // Y at most 16 columns wide (the projections against the trial or
         // test basis): MT x 2 tiles per wave, rows split over the 4 waves; a
@@ -604,19 +614,30 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
         if (a.MT <= 2) gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
         else if (a.MT == 3) gram_launch_variant<T, 3, 2>(st, a, part_cap, out, ldo, nb);
         else if (a.MT == 4) gram_launch_variant<T, 4, 2>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 5) gram_launch_variant<T, 5, 2>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 6) gram_launch_variant<T, 6, 2>(st, a, part_cap, out, ldo, nb);
-        else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 5) {
+            if (tall) gram_launch_variant<T, 5, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 5, 2>(st, a, part_cap, out, ldo, nb);
+        } else if (a.MT == 6) {
+            if (tall) gram_launch_variant<T, 6, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 6, 2>(st, a, part_cap, out, ldo, nb);
+        } else {
+            if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+        }
     } else if (a.MT <= 3)
         gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
-    else if (a.MT == 4)
-        gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
-    else if (a.MT == 5)   // two K steps in flight: more would spill registers
+    else if (a.MT == 4) {
+        if (tall) gram_launch_variant<T, 4, 4, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
+    } else if (a.MT == 5)   // two K steps in flight: more would spill registers
         gram_launch_variant<T, 5, 5, 2>(st, a, part_cap, out, ldo, nb);
-    else if (a.MT == 6)
-        gram_launch_variant<T, 6, 3>(st, a, part_cap, out, ldo, nb);
-    else
-        gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+    else if (a.MT == 6) {
+        if (tall) gram_launch_variant<T, 6, 3, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 6, 3>(st, a, part_cap, out, ldo, nb);
+    } else {
+        if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+    }
 }
 template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
                                    const double2 *, int, int, const double2 *, double2 *, size_t,

@@ -192,6 +192,27 @@ def test_gram_matches_definition(device, bx, by, dtype, n):
     assert np.array_equal(Gm, G.gram(Xd, Yd).cpu().numpy())
 
 
+@pytest.mark.parametrize("bx,by", [(64, 64), (48, 48), (32, 32), (64, 16), (40, 16), (48, 10), (40, 40)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gram_tall_blocks(device, bx, by, dtype):
+    # from 2^20 rows the wide tile sets run in their two-waves-per-SIMD build
+    # with 512 blocks; a ragged row count past the threshold
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    n = (1 << 20) + 37
+    g = torch.Generator(device="cpu").manual_seed(bx * 100 + by)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    Xd = torch.randn(n, bx, dtype=tdt, generator=g).to(device)
+    Yd = torch.randn(n, by, dtype=tdt, generator=g).to(device)
+    Gm = G.gram(Xd, Yd).cpu().numpy()
+    X = Xd.cpu().numpy().astype(np.complex128)
+    Y = Yd.cpu().numpy().astype(np.complex128)
+    ref = X.conj().T @ Y
+    scale = np.abs(X).T @ np.abs(Y)
+    assert np.max(np.abs(Gm - ref) / scale) < 1e-13
+    assert np.array_equal(Gm, G.gram(Xd, Yd).cpu().numpy())
+
+
 @pytest.mark.parametrize("wx,wy", [(1, 1), (7, 5), (10, 10), (16, 16), (40, 20), (30, 10), (10, 30),
                                    (64, 32), (64, 16), (48, 48), (16, 48), (33, 40), (128, 8)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
