@@ -192,6 +192,25 @@ def test_gram_matches_definition(device, bx, by, dtype, n):
     assert np.array_equal(Gm, G.gram(Xd, Yd).cpu().numpy())
 
 
+@pytest.mark.parametrize("w", [1, 8, 10, 16, 24, 32, 40])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gram_of_one_block(device, w, dtype):
+    # X^H X with the same block passed on both sides: bitwise the result for
+    # a copy on one side, and equal to the definition
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    g = torch.Generator(device="cpu").manual_seed(w)
+    for n in ((1000, 100003, (1 << 20) + 37) if w in (10, 32) else (1000, 100003)):
+        Xd = torch.randn(n, w + 3, dtype=tdt, generator=g).to(device)[:, 1:w + 1]
+        Gs = G.gram(Xd, Xd).cpu().numpy()
+        Gc = G.gram(Xd, Xd.clone()).cpu().numpy()
+        assert np.array_equal(Gs, Gc), n
+        X = Xd.cpu().numpy().astype(np.complex128)
+        ref = X.conj().T @ X
+        assert np.max(np.abs(Gs - ref) / (np.abs(X).T @ np.abs(X))) < 1e-13
+
+
 @pytest.mark.parametrize("bx,by", [(64, 64), (48, 48), (32, 32), (64, 16), (40, 16), (48, 10), (40, 40)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_gram_tall_blocks(device, bx, by, dtype):
