@@ -359,7 +359,7 @@ def main():
                     help="only the per-iteration timing of the named stencil workloads (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the GPLHR hot path here runs on one GPU; --gpus must be 1 (see the multi-GPU design notes)"}))
         sys.exit(2)
 
     import numpy as np
