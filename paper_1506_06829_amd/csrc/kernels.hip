@@ -985,9 +985,11 @@ static void launch_update_mfma(hipStream_t st, const UpdArgs<T> &a, int kpad) {
 
 // MFMA or VALU kernel, by measurement on the solver's shapes (4096000 and
 // 262144 rows): in FP64 the MFMA kernel is as fast or faster for every shape;
-// for complex64 it wins once the output is wider than 16 columns or Out is
-// accumulated into, and the VALU kernel's coalesced row segments win for the
-// narrow overwriting updates.
+// for complex64 it wins once the output is wider than 16 columns, Out is
+// accumulated into, or the output fills its 8- or 16-column tiles (16 -> 16
+// overwrite at 262144 rows: 25.8 -> 19.2 us, 48 -> 16: 50.4 -> 39.4 us); the
+// VALU kernel's coalesced row segments win for narrow overwrites that would
+// leave tile columns empty (10 -> 10 at 4096000 rows: 200 against 239 us).
 template <typename T>
 static bool update_mfma(const UpdArgs<T> &a, int kpad, hipStream_t st) {
     if (a.nterms < 1 || kpad < 8) return false;
@@ -1009,11 +1011,11 @@ static bool update_mfma(const UpdArgs<T> &a, int kpad, hipStream_t st) {
     } else {
         switch (nt) {
             case 1:
-                if (!use_beta) return false;
+                if (!use_beta && a.wout != 8) return false;
                 launch_update_mfma<T, 2, 1>(st, a, kpad);
                 break;
             case 2:
-                if (!use_beta) return false;
+                if (!use_beta && a.wout != 16) return false;
                 launch_update_mfma<T, 2, 2>(st, a, kpad);
                 break;
             case 3: launch_update_mfma<T, 1, 3>(st, a, kpad); break;
