@@ -791,8 +791,8 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         }
     }
     // a1: C = A - sigma B on the union pattern, its diagonal, the preconditioner
-    c_nnz = build_shifted(st, n, a_rp, a_ci, a_val, bk == B_IDENT ? 0 : 1, b_rp, b_ci, b_val,
-                          to_d2(sigma), &c_rp, &c_ci, &c_val);
+    c_nnz = build_shifted(st, n, a_nnz, a_rp, a_ci, a_val, bk == B_IDENT ? 0 : 1, bk == B_DIAG,
+                          b_rp, b_ci, b_val, to_d2(sigma), &c_rp, &c_ci, &c_val);
     c_plane = spmm_plane(st, n, c_rp, c_ci);
     if (bk == B_SPARSE) b_plane = spmm_plane(st, n, b_rp, b_ci);
     if (ik != GPLHR_PRECOND_NONE) {

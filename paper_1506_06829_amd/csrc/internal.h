@@ -126,11 +126,12 @@ void csr_validate(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *c
 int64_t csr_count_nondiag_rows(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci);
 
 // Union-pattern C = A - sigma B.  bkind: 0 identity, 1 sparse (rp/ci/val of
-// B).  Allocates rp/ci/val of C with dev_alloc on st and returns nnz(C).
-int64_t build_shifted(hipStream_t st, int64_t n, const int32_t *arp, const int32_t *aci,
-                      const double2 *aval, int bkind, const int32_t *brp, const int32_t *bci,
-                      const double2 *bval, double2 sigma, int32_t **crp, int32_t **cci,
-                      double2 **cval);
+// B); bdiag: B stores exactly its diagonal, one entry per row.  anz = nnz(A).
+// Allocates rp/ci/val of C with dev_alloc on st and returns nnz(C).
+int64_t build_shifted(hipStream_t st, int64_t n, int64_t anz, const int32_t *arp,
+                      const int32_t *aci, const double2 *aval, int bkind, bool bdiag,
+                      const int32_t *brp, const int32_t *bci, const double2 *bval,
+                      double2 sigma, int32_t **crp, int32_t **cci, double2 **cval);
 // d[i] = C(i,i) (0 when not stored); returns the number of zero diagonal entries.
 int64_t extract_diag(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci,
                      const double2 *val, double2 *d);
