@@ -750,10 +750,22 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         throw Error(-1, "Jacobi needs sweeps >= 1 and 0 < omega < 2");
     if (!std::isfinite(sigma.real()) || !std::isfinite(sigma.imag())) throw Error(-1, "sigma must be finite");
 
+    // pinned staging for every small host <-> device transfer of the handle
+    hpin_bytes = sizeof(double2) * 4 * 64 * 64 + 4096;
+    hpin = static_cast<double2 *>(pinned_alloc(hpin_bytes));
+    // row_ptr[0] and row_ptr[n] of a CSR, both read with one synchronisation
+    auto row_ptr_ends = [&](const int32_t *rp, int32_t *ends) {
+        int32_t *he = reinterpret_cast<int32_t *>(hpin);
+        GPLHR_HIP_CHECK(hipMemcpyAsync(he, rp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(he + 1, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        ends[0] = he[0];
+        ends[1] = he[1];
+    };
+
     // A: validate and keep a copy (pattern + values) for the backward pass
     int32_t ends[2];
-    GPLHR_HIP_CHECK(hipMemcpy(&ends[0], A->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
-    GPLHR_HIP_CHECK(hipMemcpy(&ends[1], A->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+    row_ptr_ends(A->row_ptr, ends);
     if (ends[0] != 0 || ends[1] != A->nnz) throw Error(-1, "A: row_ptr[0] must be 0 and row_ptr[n] = nnz");
     int64_t bad_rows = 0, bad_vals = 0;
     csr_validate(st, n, A->row_ptr, A->col_idx, static_cast<const double2 *>(A->val), &bad_rows, &bad_vals);
@@ -770,8 +782,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         if (!B->row_ptr || !B->col_idx || !B->val) throw Error(-1, "B must be a device CSR");
         if (B->n != n) throw Error(-1, "A and B must have the same order");
         if (B->nnz < 0 || B->nnz > INT32_MAX) throw Error(-1, "nnz(B) out of range");
-        GPLHR_HIP_CHECK(hipMemcpy(&ends[0], B->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
-        GPLHR_HIP_CHECK(hipMemcpy(&ends[1], B->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+        row_ptr_ends(B->row_ptr, ends);
         if (ends[0] != 0 || ends[1] != B->nnz) throw Error(-1, "B: row_ptr[0] must be 0 and row_ptr[n] = nnz");
         csr_validate(st, n, B->row_ptr, B->col_idx, static_cast<const double2 *>(B->val), &bad_rows, &bad_vals);
         if (bad_rows) throw Error(-1, "B: " + std::to_string(bad_rows) + " malformed rows");
@@ -870,8 +881,6 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         hgm = static_cast<double2 *>(pinned_alloc(hgm_bytes));
     }
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
-    hpin_bytes = sizeof(double2) * 4 * 64 * 64 + 4096;
-    hpin = static_cast<double2 *>(pinned_alloc(hpin_bytes));
 
     // V0 -> Z(:, 0:b), then steps 1-4
     if (opt.V0)
