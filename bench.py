@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-named", action="store_true", help="skip the named stencil workloads")
     ap.add_argument("--scale", type=int, default=None, help="override n of the default workload")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the block-update and Gram probes (for profiling)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="only the SpMM bandwidth measurement on the 160^3 operator (for profiling)")
     ap.add_argument("--no-next", action="store_true", help="skip the extension rows")
@@ -381,6 +383,18 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"spmm_160cube_b16": res, "copy_bytes_each_way": x.numel() * 8}), flush=True)
+        return
+
+    if args.kernels_only:
+        # the block-update and Gram probes of the bench line, then the same
+        # device copy as --spmm-only for scaling hardware byte counters
+        out = kernel_rooflines(G, torch)
+        x = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"other_kernel_rooflines": out, "copy_bytes_each_way": x.numel() * 8}), flush=True)
         return
 
     if args.named_only:
