@@ -235,6 +235,29 @@ def test_converged_parity_small(device, name, precision):
         assert stats["fp64_iterations"] < stats["iterations"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_parity_missing_diagonal(device, precision):
+    # every third row of A without its diagonal entry: C = A - sigma B is
+    # built by the row merge on the union pattern instead of the diagonal
+    # shift of a copy of A
+    import dataclasses
+    p = problems.config("d1", 3000)
+    S = p.A.to_scipy().tocoo()
+    keep = ~((S.row == S.col) & (S.row % 3 == 0))
+    A2 = problems.csr_from_scipy(sp.coo_matrix((S.data[keep], (S.row[keep], S.col[keep])),
+                                               shape=S.shape))
+    assert A2.nnz < p.A.nnz
+    p = dataclasses.replace(p, A=A2)
+    s, _, _ = gpu_solver(p, precision=precision, max_iter=100)
+    st, nconv, res = s.iterate()
+    out = s.schur()
+    s.close()
+    assert st == 0 and nconv == p.k and res <= 1e-10
+    ref = O.solve_problem(p, tol=1e-10, maxit=100)
+    assert ref.converged
+    assert match_err(out["lam"][:p.k], ref.lam[:p.k]) < 1e-10
+
+
 @functools.lru_cache(maxsize=None)
 def _d1_reference():
     ref = O.solve_problem(problems.config("d1"), tol=1e-10, maxit=100)
