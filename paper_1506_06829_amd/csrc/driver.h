@@ -91,7 +91,9 @@ struct Ctx {
     // coefficients of the S recursion: M_B, sigma M_B - M_A (Algorithm 2, the
     // same buffers as M1, M2) or Lambda_B, sigma Lambda_B - Lambda_A (Algorithm 3)
     double2 *M1s = nullptr, *M2s = nullptr;
-    double2 *F1 = nullptr, *F2 = nullptr, *dZr = nullptr, *dlam = nullptr, *rnorm = nullptr;
+    // F1 holds the projected pencil's two blocks (F2 follows F1); dZr holds
+    // the Ritz coefficients followed by the eigenvalues
+    double2 *F1 = nullptr, *dZr = nullptr, *rnorm = nullptr;
     double2 *gmH = nullptr, *gmY = nullptr;   // block GMRES small factors (device)
     double2 *hgm = nullptr;                   // their pinned host staging
     size_t hgm_bytes = 0;

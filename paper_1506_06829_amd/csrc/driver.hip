@@ -51,7 +51,7 @@ Ctx::~Ctx() {
     for (Work<double2> *w : {&wd}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     for (Work<float2> *w : {&wf}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(coefL, st);
-    dfree(M1, st); dfree(M2, st); dfree(M1s, st); dfree(M2s, st); dfree(F1, st); dfree(F2, st); dfree(dZr, st); dfree(dlam, st); dfree(rnorm, st);
+    dfree(M1, st); dfree(M2, st); dfree(M1s, st); dfree(M2s, st); dfree(F1, st); dfree(dZr, st); dfree(rnorm, st);
     dfree(dstatus, st); dfree(gmH, st); dfree(gmY, st);
     // the staging buffers go back to the free list only once the stream has
     // finished with them (dev_free above waited for it)
@@ -336,11 +336,12 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     const T *bsrc = bexp() ? w.BZ : w.Z;
     const T *bsc = bscale<T>();
     // a8: F1 = U^H (A - sigma B) Z, F2 = U^H B Z   (s_cur x s_cur, FP64)
+    // F2 follows F1 in one buffer, so both come back in one copy
+    const size_t ss = (size_t)s_cur * s_cur;
+    double2 *F2 = F1 + ss;
     gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
     gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
-    const size_t ss = (size_t)s_cur * s_cur;
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, F1, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + ss, F2, ss * sizeof(double2), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, F1, 2 * ss * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + 2 * ss, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     tflush();
@@ -617,11 +618,11 @@ void Ctx::check() {
     const int ld = smax;
     const T *bsrc = bexp() ? w.BZ : w.Z;
     const T *bsc = bscale<T>();
-    gram<T>(w.Z, ld, b, w.CZ, ld, b, nullptr, g0);
-    gram<T>(w.Z, ld, b, bsrc, ld, b, bsc, g1);
+    // the two Grams side by side in g0, so they come back in one copy
     const size_t bb = (size_t)b * b;
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, g0, bb * sizeof(double2), hipMemcpyDeviceToHost, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb, g1, bb * sizeof(double2), hipMemcpyDeviceToHost, st));
+    gram<T>(w.Z, ld, b, w.CZ, ld, b, nullptr, g0);
+    gram<T>(w.Z, ld, b, bsrc, ld, b, bsc, g0 + bb);
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, g0, 2 * bb * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     Mat Va(b, b), Vb(b, b);
     std::memcpy(Va.data(), hpin, bb * sizeof(cd));
@@ -673,13 +674,13 @@ void Ctx::check() {
     }
     lam_h = lam;
     Zr_h = Zr;
+    // Zr and the eigenvalues in one upload (dZr holds both)
     std::memcpy(hpin, Zr.data(), bb * sizeof(cd));
     std::memcpy(hpin + bb, lam.data(), b * sizeof(cd));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(dZr, hpin, bb * sizeof(double2), hipMemcpyHostToDevice, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(dlam, hpin + bb, b * sizeof(double2), hipMemcpyHostToDevice, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(dZr, hpin, (bb + b) * sizeof(double2), hipMemcpyHostToDevice, st));
     const int nblk = launch_resid_partials<T>(st, n, b, w.CZ, ld, w.Z, ld,
                                               bexp() ? w.BZ : nullptr, ld, bsc,
-                                              to_d2(sigma), dZr, dlam, part, RESID_BLOCKS);
+                                              to_d2(sigma), dZr, dZr + bb, part, RESID_BLOCKS);
     launch_reduce_partials(st, part, nblk, b, 1, rnorm, b);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + bb + b, rnorm, b * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
@@ -872,8 +873,8 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     dalloc(&part, PART_CAP, st);
     dalloc(&g0, 64 * 64, st); dalloc(&g1, 64 * 64, st); dalloc(&rinv, 64 * 64, st);
     dalloc(&coefY, 64 * 64, st); dalloc(&coefL, 64 * 64, st);
-    dalloc(&M1, 64 * 64, st); dalloc(&M2, 64 * 64, st); dalloc(&M1s, 64 * 64, st); dalloc(&M2s, 64 * 64, st); dalloc(&F1, 64 * 64, st); dalloc(&F2, 64 * 64, st);
-    dalloc(&dZr, 64 * 64, st); dalloc(&dlam, 64, st); dalloc(&rnorm, 64, st); dalloc(&dstatus, 1, st);
+    dalloc(&M1, 64 * 64, st); dalloc(&M2, 64 * 64, st); dalloc(&M1s, 64 * 64, st); dalloc(&M2s, 64 * 64, st); dalloc(&F1, 2 * 64 * 64, st);
+    dalloc(&dZr, 64 * 64 + 64, st); dalloc(&rnorm, 64, st); dalloc(&dstatus, 1, st);
     if (gm) {
         dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT, st);
         dalloc(&gmY, 64 * 16, st);
