@@ -87,7 +87,11 @@ struct Ctx {
 
     // small device buffers (FP64 complex)
     double2 *part = nullptr, *g0 = nullptr, *g1 = nullptr, *rinv = nullptr;
-    double2 *coefY = nullptr, *coefL = nullptr, *M1 = nullptr, *M2 = nullptr;
+    double2 *coefY = nullptr, *M1 = nullptr, *M2 = nullptr;
+    // packed [Y_R Y_P | Y_L | M_B | sigma M_B - M_A] of the last Schur step
+    // (uploaded in one copy); M1c, M2c point at its M_B and sigma M_B - M_A
+    double2 *cpack = nullptr;
+    const double2 *M1c = nullptr, *M2c = nullptr;
     // coefficients of the S recursion: M_B, sigma M_B - M_A (Algorithm 2, the
     // same buffers as M1, M2) or Lambda_B, sigma Lambda_B - Lambda_A (Algorithm 3)
     double2 *M1s = nullptr, *M2s = nullptr;

@@ -50,7 +50,7 @@ Ctx::~Ctx() {
     dfree(bd, st); dfree(bd32, st); dfree(dinv, st); dfree(dinv32, st); dfree(dw, st); dfree(dw32, st);
     for (Work<double2> *w : {&wd}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     for (Work<float2> *w : {&wf}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
-    dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(coefL, st);
+    dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(cpack, st);
     dfree(M1, st); dfree(M2, st); dfree(M1s, st); dfree(M2s, st); dfree(F1, st); dfree(dZr, st); dfree(rnorm, st);
     dfree(dstatus, st); dfree(gmH, st); dfree(gmY, st);
     // the staging buffers go back to the free list only once the stream has
@@ -426,14 +426,16 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     off += (size_t)b * b;
     std::memcpy(hpin + off, m2.data(), (size_t)b * b * sizeof(cd));
     off += (size_t)b * b;
-    GPLHR_HIP_CHECK(hipMemcpyAsync(coefY, hpin, (size_t)s_cur * nc * sizeof(double2), hipMemcpyHostToDevice, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(coefL, hpin + (size_t)s_cur * nc, (size_t)s_cur * b * sizeof(double2), hipMemcpyHostToDevice, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(M1, hpin + (size_t)s_cur * (nc + b), (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(M2, hpin + (size_t)s_cur * (nc + b) + (size_t)b * b, (size_t)b * b * sizeof(double2), hipMemcpyHostToDevice, st));
+    // one upload of the packed coefficients; M_B and sigma M_B - M_A stay in
+    // cpack for the next iteration's residual blocks (M1c, M2c)
+    GPLHR_HIP_CHECK(hipMemcpyAsync(cpack, hpin, off * sizeof(double2), hipMemcpyHostToDevice, st));
+    const double2 *cY = cpack, *cL = cpack + (size_t)s_cur * nc;
+    M1c = cL + (size_t)s_cur * b;
+    M2c = M1c + (size_t)b * b;
     // a10: V = Z Y_R, P = Z Y_P (and the same for CZ, BZ); Q = U Y_L.  P lands
     // at its between-iterations slot smax - b.
     UpdTerm<T> t;
-    t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
+    t.ld = ld; t.col = 0; t.w = s_cur; t.M = cY; t.ldm = s_cur;
     t.in = w.Z;
     update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
     // C V and B V only: C P and B P are formed afresh after step 22
@@ -443,7 +445,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         t.in = w.BZ;
         update<T>(w.BZ, ld, b, 0, b, offP, false, 1, &t);
     }
-    t.in = w.U; t.M = coefL;
+    t.in = w.U; t.M = cL;
     update<T>(w.U, ld, b, 0, b, 0, false, 1, &t);
     // The host writes the pinned staging buffer again only after a stream
     // synchronisation, so the uploads above cannot be overtaken.
@@ -558,9 +560,10 @@ void Ctx::iterate_once() {
         cprod<T>(Z + dst, ld, CZ + dst, ld, a);
         bprod<T>(Z + dst, ld, BZ + dst, ld, a);
     };
-    build(0, b, M1, M2, q * b, offW);                                // W (steps 6-12)
+    const double2 *m1 = eig ? M1 : M1c, *m2 = eig ? M2 : M2c;
+    build(0, b, m1, m2, q * b, offW);                                // W (steps 6-12)
     for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
-        build(offW + (l - 1) * a, a, eig ? M1s : M1, eig ? M2s : M2, q + q * b, offW + l * a);
+        build(offW + (l - 1) * a, a, eig ? M1s : m1, eig ? M2s : m2, q + q * b, offW + l * a);
 
     // step 22: P <- orth(P - [V W S][V W S]^H P), then C P (and B P)
     if (pa > 0) {
@@ -872,7 +875,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     }
     dalloc(&part, PART_CAP, st);
     dalloc(&g0, 64 * 64, st); dalloc(&g1, 64 * 64, st); dalloc(&rinv, 64 * 64, st);
-    dalloc(&coefY, 64 * 64, st); dalloc(&coefL, 64 * 64, st);
+    dalloc(&coefY, 64 * 64, st); dalloc(&cpack, 4 * 64 * 64, st);
     dalloc(&M1, 64 * 64, st); dalloc(&M2, 64 * 64, st); dalloc(&M1s, 64 * 64, st); dalloc(&M2s, 64 * 64, st); dalloc(&F1, 2 * 64 * 64, st);
     dalloc(&dZr, 64 * 64 + 64, st); dalloc(&rnorm, 64, st); dalloc(&dstatus, 1, st);
     if (gm) {
