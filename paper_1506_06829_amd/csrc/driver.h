@@ -95,6 +95,8 @@ struct Ctx {
     // coefficients of the S recursion: M_B, sigma M_B - M_A (Algorithm 2, the
     // same buffers as M1, M2) or Lambda_B, sigma Lambda_B - Lambda_A (Algorithm 3)
     double2 *M1s = nullptr, *M2s = nullptr;
+    // owners of M1, M2, M1s, M2s (mbase) and of dstatus, F1 (fbase)
+    double2 *mbase = nullptr, *fbase = nullptr;
     // F1 holds the projected pencil's two blocks (F2 follows F1); dZr holds
     // the Ritz coefficients followed by the eigenvalues
     double2 *F1 = nullptr, *dZr = nullptr, *rnorm = nullptr;

@@ -51,8 +51,8 @@ Ctx::~Ctx() {
     for (Work<double2> *w : {&wd}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     for (Work<float2> *w : {&wf}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(cpack, st);
-    dfree(M1, st); dfree(M2, st); dfree(M1s, st); dfree(M2s, st); dfree(F1, st); dfree(dZr, st); dfree(rnorm, st);
-    dfree(dstatus, st); dfree(gmH, st); dfree(gmY, st);
+    dfree(mbase, st); dfree(fbase, st); dfree(dZr, st); dfree(rnorm, st);
+    dfree(gmH, st); dfree(gmY, st);
     // the staging buffers go back to the free list only once the stream has
     // finished with them (dev_free above waited for it)
     (void)hipStreamSynchronize(st);
@@ -341,20 +341,19 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     double2 *F2 = F1 + ss;
     gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
     gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, F1, 2 * ss * sizeof(double2), hipMemcpyDeviceToHost, st));
-    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin + 2 * ss, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, fbase, (1 + 2 * ss) * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     tflush();
     {
         int stv = 0;
-        std::memcpy(&stv, hpin + 2 * ss, sizeof(int));
+        std::memcpy(&stv, hpin, sizeof(int));
         n_breakdown = stv;
     }
     // a9: ordered generalized Schur form on the host (FP64)
     auto t0 = std::chrono::steady_clock::now();
     Mat K(s_cur, s_cur), Gm(s_cur, s_cur);
-    std::memcpy(K.data(), hpin, ss * sizeof(cd));
-    std::memcpy(Gm.data(), hpin + ss, ss * sizeof(cd));
+    std::memcpy(K.data(), hpin + 1, ss * sizeof(cd));
+    std::memcpy(Gm.data(), hpin + 1 + ss, ss * sizeof(cd));
     for (const cd &v : K.a)
         if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
             throw Error(-6, "non-finite entries in the projected pencil");
@@ -668,10 +667,7 @@ void Ctx::check() {
             mh[2 * bb + j + (size_t)j * b] = beta_h[j];
             mh[3 * bb + j + (size_t)j * b] = m2d;
         }
-        GPLHR_HIP_CHECK(hipMemcpyAsync(M1, mh, bb * sizeof(double2), hipMemcpyHostToDevice, st));
-        GPLHR_HIP_CHECK(hipMemcpyAsync(M2, mh + bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
-        GPLHR_HIP_CHECK(hipMemcpyAsync(M1s, mh + 2 * bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
-        GPLHR_HIP_CHECK(hipMemcpyAsync(M2s, mh + 3 * bb, bb * sizeof(double2), hipMemcpyHostToDevice, st));
+        GPLHR_HIP_CHECK(hipMemcpyAsync(M1, mh, 4 * bb * sizeof(double2), hipMemcpyHostToDevice, st));
     } else {
         if (!small::ritz(Va, Vb, sigma, lam, Zr)) throw Error(-6, "Rayleigh-Ritz step failed");
     }
@@ -876,8 +872,15 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     dalloc(&part, PART_CAP, st);
     dalloc(&g0, 64 * 64, st); dalloc(&g1, 64 * 64, st); dalloc(&rinv, 64 * 64, st);
     dalloc(&coefY, 64 * 64, st); dalloc(&cpack, 4 * 64 * 64, st);
-    dalloc(&M1, 64 * 64, st); dalloc(&M2, 64 * 64, st); dalloc(&M1s, 64 * 64, st); dalloc(&M2s, 64 * 64, st); dalloc(&F1, 2 * 64 * 64, st);
-    dalloc(&dZr, 64 * 64 + 64, st); dalloc(&rnorm, 64, st); dalloc(&dstatus, 1, st);
+    // M_B-type coefficient blocks of Algorithm 3, side by side (one upload)
+    dalloc(&mbase, 4 * 64 * 64, st);
+    M1 = mbase; M2 = M1 + (size_t)b * b; M1s = M2 + (size_t)b * b; M2s = M1s + (size_t)b * b;
+    // [status | F1 | F2]: the breakdown counter and the projected pencil come
+    // back in one copy
+    dalloc(&fbase, 1 + 2 * 64 * 64, st);
+    dstatus = reinterpret_cast<int *>(fbase);
+    F1 = fbase + 1;
+    dalloc(&dZr, 64 * 64 + 64, st); dalloc(&rnorm, 64, st);
     if (gm) {
         dalloc(&gmH, (size_t)(pre.steps + 1) * 4 * GM_SLOT, st);
         dalloc(&gmY, 64 * 16, st);
