@@ -5,8 +5,20 @@ this module.  The product path (the HIP library and its Python binding) never
 calls it, and shares no code with it.
 
 It implements the Schur-vector form of the Generalized Preconditioned Locally
-Harmonic Residual method (Vecharynski, Yang, Xue; Algorithm 2 of Section 3.5,
-"The GPLHR algorithm") step by step, with numpy/scipy primitives:
+Harmonic Residual method (Vecharynski, Yang, Xue; Section 3, "The GPLHR
+algorithm" of Section 3.5) from the equations that define each part, with
+numpy/scipy primitives:
+
+* the trial subspace of Section 3.1: the generalized Sylvester correction
+  operator L and right-hand side F (eq. operator), the projected
+  preconditioner T_L (eq. prec_gen / eq. prec) and the Krylov-Arnoldi
+  sequence of T_L L (Algorithm 1, eq. krylov_sep_block), augmented by P
+  (eq. trial_partial1, eq. P1);
+* the test subspace and the harmonic Schur-Rayleigh-Ritz step of Section 3.3
+  (eq. proj_schur, Proposition 3.2);
+* the Q-free factors of Theorem 2.2 (eq. M, eqs. G1_fix / G2_fix).
+
+Primitives:
 
 * sparse products:  scipy.sparse CSR times a dense block,
 * ``orth``:         Householder QR (scipy.linalg.qr, economic),
@@ -37,11 +49,12 @@ DESIGN.md as well):
 * First iteration: P is empty, so the trial space has (m+2)b columns.
 * Block width b may exceed k; the k leading pairs decide convergence.
 
-Parity pins: see tests/test_oracle.py (closed-form spectrum of the 2-D
-upwind stencil, dense QZ eigenvalues of small pencils, the Schur-form and
+Parity pins: see tests/test_oracle.py (closed-form spectra of the 2-D and
+3-D upwind stencils, dense QZ eigenvalues of small pencils, the Schur-form and
 Q-free-form invariants of Section 2, Propositions 3.1 and 3.2, the residual
-identity that follows Algorithm 2, exact-preconditioner and full-space special
-cases).
+identity that follows Algorithm 2, the Krylov-Arnoldi sequence against the
+correction operator and T_L assembled densely in Kronecker form,
+exact-preconditioner and full-space special cases).
 """
 from __future__ import annotations
 
@@ -233,6 +246,89 @@ def ritz_pairs(A, B, V: np.ndarray, sigma: complex):
 
 
 # --------------------------------------------------------------------------
+# Section 3.1: the correction equation and its preconditioned Krylov space
+# --------------------------------------------------------------------------
+
+def projector(Y: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+    """X -> (I - Y Y^*) X: the orthogonal projector onto the complement of
+    col{Y} (Y with orthonormal columns)."""
+    return lambda X: X - Y @ (Y.conj().T @ X)
+
+
+def left_basis(V: np.ndarray, Q: np.ndarray, standard: bool) -> np.ndarray:
+    """The basis whose complement is the range of the correction operator:
+    the left Schur basis Q of the generalized problem (eq. sylvester), the
+    right basis V itself when B = I (eq. sylvester_st)."""
+    return V if standard else Q
+
+
+def correction_rhs(A, Bmul, X: np.ndarray, L: np.ndarray, MA: np.ndarray,
+                   MB: np.ndarray) -> np.ndarray:
+    """F of eq. operator: minus the projected residual of the Q-free Schur
+    form (eq. gschur2), -(I - L L^*)(A X M_B - B X M_A).  With locking, M_A and
+    M_B are the columns of the active (trailing) pairs."""
+    return -projector(L)(A @ X @ MB - Bmul(X) @ MA)
+
+
+def sylvester_operator(A, Bmul, V: np.ndarray, L: np.ndarray, MA: np.ndarray,
+                       MB: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+    """The generalized Sylvester operator of eq. operator,
+    C -> (P_L A P_V) C M_B - (P_L B P_V) C M_A, with P_Y = I - Y Y^*
+    (eq. sylvester for B != I, eq. sylvester_st with L = V for B = I)."""
+    PV, PL = projector(V), projector(L)
+
+    def apply(C: np.ndarray) -> np.ndarray:
+        Cp = PV(C)
+        return PL(A @ Cp @ MB - Bmul(Cp) @ MA)
+    return apply
+
+
+def projected_preconditioner(T: Callable, V: np.ndarray, L: np.ndarray,
+                             right_projector: bool = True) -> Callable:
+    """T_L of eq. prec_gen (eq. prec for B = I): (I - V V^*) T (I - L L^*).
+    Without the right projector it is (I - V V^*) T, the variant of Table 3."""
+    PV, PL = projector(V), projector(L)
+    if right_projector:
+        return lambda X: PV(T(PL(X)))
+    return lambda X: PV(T(X))
+
+
+def krylov_arnoldi(TL: Callable, Lop: Callable, F: np.ndarray, m: int):
+    """Algorithm 1: the Krylov-Arnoldi sequence K = [W, S_1, ..., S_m] of the
+    operator T_L L started at T_L F (eq. krylov_sep_block).  W = orth(T_L F);
+    each S_l is T_L L(S_{l-1}) (S_0 = W) made orthogonal to W and to the
+    earlier S_j, then orthonormalised."""
+    W = orth(TL(F))
+    S: list = []
+    prev = W
+    for _ in range(m):
+        Sl = TL(Lop(prev))
+        Sl = Sl - W @ (W.conj().T @ Sl)
+        for Sj in S:
+            Sl = Sl - Sj @ (Sj.conj().T @ Sl)
+        Sl = orth(Sl)
+        S.append(Sl)
+        prev = Sl
+    return W, S
+
+
+def augment(P: np.ndarray, blocks) -> np.ndarray:
+    """The extra block of eq. trial_partial1 made orthonormal against the
+    rest of the trial basis: P minus its components along each block, then
+    orthonormalised."""
+    for Y in blocks:
+        P = P - Y @ (Y.conj().T @ P)
+    return orth(P)
+
+
+def harmonic_test_basis(C, Q: np.ndarray, Z_new: np.ndarray) -> np.ndarray:
+    """U = [Q, Qhat], an orthonormal basis of (A - sigma B) Z whose leading
+    block is Q (Proposition 3.2: C V lies in col{Q}); Qhat spans the part of
+    C Z_new orthogonal to Q, Z_new being the trial blocks after V."""
+    return np.hstack([Q, orth(projector(Q)(C @ Z_new))])
+
+
+# --------------------------------------------------------------------------
 # Algorithm 2
 # --------------------------------------------------------------------------
 
@@ -296,11 +392,11 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
     def Bx(X):
         return X if std else Bm @ X
 
-    # step 1
+    # initial bases: V = orth(V0), Q = orth((A - sigma B) V), then their
+    # ordered Schur form and the Q-free factors (Theorem 2.2)
     V = orth(V0)
     Q = orth(C @ V)
     P = None
-    # steps 2-4
     RA, RB, YL, YR = ordqz(Q.conj().T @ (A @ V), Q.conj().T @ Bx(V), sigma)
     V = V @ YR
     Q = Q @ YL
@@ -327,77 +423,47 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
             m = min((m0 * b) // (b - q), m_max)
         a = b - q
         lock_history.append((q, m))
-        MAa, MBa = MA[q:, q:], MB[q:, q:]
         if P is not None:
             P = P[:, :a]
-
-        def proj_V(X):
-            return X - V @ (V.conj().T @ X)
-
-        def proj_left(X):   # I - QQ^* for B != I, I - VV^* for B = I
-            if not proj_before_T:
-                return X
-            Y = V if std else Q
-            return X - Y @ (Y.conj().T @ X)
-
-        # steps 6-10: projected preconditioned residual (active columns q..b-1)
-        if not std:
-            WA = A @ V - Q @ RA
-            WB = Bm @ V - Q @ RB
-            W = proj_V(precond(proj_left((WA @ MB - WB @ MA)[:, q:])))
-        else:
-            W = proj_V(precond(proj_left((A @ V @ MB - V @ MA)[:, q:])))
-        # step 12
-        W = orth(W)
-        S_prev = W
-        S = np.zeros((V.shape[0], 0), dtype=complex)
-        # steps 13-21: Krylov-Arnoldi blocks
-        for _ in range(m):
-            Sl = proj_V(precond(proj_left(A @ S_prev @ MBa - Bx(S_prev) @ MAa)))
-            Sl = Sl - W @ (W.conj().T @ Sl)
-            Sl = Sl - S @ (S.conj().T @ Sl)
-            Sl = orth(Sl)
-            S = np.hstack([S, Sl])
-            S_prev = Sl
-        # step 22
+        # trial subspace (Section 3.1): the correction equation of the a
+        # active pairs, L(C) = F with V^* C = 0 (eq. operator), and the
+        # Krylov-Arnoldi sequence of T_L L from T_L F (Algorithm 1)
+        L = left_basis(V, Q, std)
+        Lop = sylvester_operator(A, Bx, V, L, MA[q:, q:], MB[q:, q:])
+        F = correction_rhs(A, Bx, V, L, MA[:, q:], MB[:, q:])
+        TL = projected_preconditioner(precond, V, L, proj_before_T)
+        W, S_list = krylov_arnoldi(TL, Lop, F, m)
+        S = np.hstack(S_list)
+        # the extra search directions of eq. trial_partial1 (Section 3.4)
         if P is not None:
-            P = P - V @ (V.conj().T @ P)
-            P = P - W @ (W.conj().T @ P)
-            P = P - S @ (S.conj().T @ P)
-            P = orth(P)
-        # step 23: trial subspace
-        blocks = [V, W, S] + ([P] if P is not None else [])
-        Z = np.hstack(blocks)
-        # step 24: test subspace, projected first, then orthonormalised
-        Qh = C @ Z[:, b:]
-        Qh = Qh - Q @ (Q.conj().T @ Qh)
-        Qh = orth(Qh)
-        U = np.hstack([Q, Qh])
-        # step 25: harmonic Schur-Rayleigh-Ritz
-        F = U.conj().T @ (A @ Z)
+            P = augment(P, [V, W, S])
+        Z = np.hstack([V, W, S] + ([P] if P is not None else []))
+        # test subspace (Section 3.3, Proposition 3.2)
+        U = harmonic_test_basis(C, Q, Z[:, b:])
+        # harmonic Schur-Rayleigh-Ritz (Section 3.3, eq. proj_schur): ordered
+        # generalized Schur form of the projected pencil (U^* A Z, U^* B Z)
+        Fp = U.conj().T @ (A @ Z)
         Gm = U.conj().T @ Bx(Z)
-        RAb, RBb, YLb, YRb = ordqz(F, Gm, sigma)
-        # step 26
-        YR = YRb[:, :b]
-        YL = YLb[:, :b]
+        RAb, RBb, YLb, YRb = ordqz(Fp, Gm, sigma)
         RA = RAb[:b, :b]
         RB = RBb[:b, :b]
-        # steps 27-28: V = Z Y_R (= V Y_V + W Y_W + S Y_S + P Y_P), Q = U Y_L
+        state_in = dict(V_in=V, Q_in=Q, MA_in=MA, MB_in=MB, W=W, S=S_list, q=q)
+        # new approximate Schur bases V = Z Y_R, Q = U Y_L
         V_old = V
-        V = Z @ YR
-        Q = U @ YL
-        # step 29: thick restart (or the LOBPCG-style direction)
+        V = Z @ YRb[:, :b]
+        Q = U @ YLb[:, :b]
+        # P: thick restart (eq. P1), the previous V (eq. P_lobpcg), or none
         if p_mode == "thick":
             P = Z @ YRb[:, b:b + a]
         elif p_mode == "lobpcg":
             P = V_old[:, q:]
         else:
             P = None
-        # steps 30-31
+        # Q-free factors of the new Schur form (Theorem 2.2, eq. M)
         MA, MB, _ = q_free_factors(RA, RB)
         if keep_trace:
-            trace.append(dict(Z=Z, U=U, F=F, G=Gm, RAb=RAb, RBb=RBb, YLb=YLb, YRb=YRb,
-                              V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB))
+            trace.append(dict(Z=Z, U=U, F=Fp, G=Gm, RAb=RAb, RBb=RBb, YLb=YLb, YRb=YRb,
+                              V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB, **state_in))
 
     return GplhrResult(V=V, Q=Q, RA=RA, RB=RB, MA=MA, MB=MB, lam=lam, X=X, rho=rho,
                        iterations=it, converged=bool(np.max(rho[:k]) <= tol),
@@ -452,7 +518,6 @@ def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
     Bm = sp.identity(A.shape[0], format="csr", dtype=complex) if std else sp.csr_matrix(B)
     C = (A - sigma * Bm).tocsr()
     b = X0.shape[1]
-    # steps 1-2
     X, AX, BX, alpha, beta = _unit_columns_and_forms(A, Bm, X0.astype(complex))
     Q = C @ X
     P = None
@@ -468,47 +533,28 @@ def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
         if np.max(rho[:k]) <= tol or it >= maxit:
             break
         it += 1
-        # step 4
+        # orthonormal bases of the current X and of (A - sigma B) X
         V = orth(X)
         Q = orth(Q)
-        L = V if std else Q
-
-        def proj_V(Y):
-            return Y - V @ (V.conj().T @ Y)
-
-        def proj_left(Y):
-            return Y - L @ (L.conj().T @ Y)
-
-        # steps 5-9: W = (I - VV^*) T (I - QQ^*) (A X Lambda_B - B X Lambda_A)
-        W = orth(proj_V(precond(proj_left(AX * beta[None, :] - BX * alpha[None, :]))))
-        # steps 10-17
-        S_prev = W
-        S = np.zeros((A.shape[0], 0), dtype=complex)
-        for _ in range(m):
-            Sl = proj_V(precond(proj_left((A @ S_prev) * beta[None, :]
-                                          - (Bm @ S_prev) * alpha[None, :])))
-            Sl = Sl - W @ (W.conj().T @ Sl)
-            Sl = Sl - S @ (S.conj().T @ Sl)
-            Sl = orth(Sl)
-            S = np.hstack([S, Sl])
-            S_prev = Sl
-        # step 18
+        # the correction equation with the diagonal forms Lambda_A, Lambda_B in
+        # place of M_A, M_B, and its Krylov-Arnoldi sequence (Algorithm 1)
+        L = left_basis(V, Q, std)
+        LA, LB = np.diag(alpha), np.diag(beta)
+        Lop = sylvester_operator(A, lambda Y: Bm @ Y, V, L, LA, LB)
+        F = correction_rhs(A, lambda Y: Bm @ Y, X, L, LA, LB)
+        W, S_list = krylov_arnoldi(projected_preconditioner(precond, V, L), Lop, F, m)
+        S = np.hstack(S_list)
         if P is not None:
-            P = P - V @ (V.conj().T @ P)
-            P = P - W @ (W.conj().T @ P)
-            P = P - S @ (S.conj().T @ P)
-            P = orth(P)
-        # steps 19-21
+            P = augment(P, [V, W, S])
         Z = np.hstack([V, W, S] + ([P] if P is not None else []))
-        Qh = C @ Z[:, b:]
-        Qh = Qh - Q @ (Q.conj().T @ Qh)
-        U = np.hstack([Q, orth(Qh)])
-        # steps 22-23: eigenvectors of (U^* A Z, U^* B Z), nearest sigma first
+        U = harmonic_test_basis(C, Q, Z[:, b:])
+        # eigenvectors of the projected pencil (U^* A Z, U^* B Z), nearest sigma first
         ev, Yb = sla.eig(U.conj().T @ (A @ Z), U.conj().T @ (Bm @ Z), homogeneous_eigvals=True)
         d = np.array([_dist(ev[0][j], ev[1][j], sigma) for j in range(ev.shape[1])])
         Yb = Yb[:, np.argsort(d, kind="stable")]
         Y = Yb[:, :b]
-        # steps 24-26
+        # new X from the leading eigenvectors; P from the next ones (thick
+        # restart) or from the non-V part of X (LOBPCG-style direction)
         Pn = Z[:, b:] @ Y[b:, :]
         X = V @ Y[:b, :] + Pn
         Q = C @ X
@@ -518,7 +564,7 @@ def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
             P = Pn
         else:
             P = None
-        # step 27
+        # unit columns and the diagonal forms diag(X^* A X), diag(X^* B X)
         X, AX, BX, alpha, beta = _unit_columns_and_forms(A, Bm, X)
     return GplhrEigResult(X=X, alpha=alpha, beta=beta, lam=lam, rho=rho, iterations=it,
                           converged=bool(np.max(rho[:k]) <= tol), history=history,

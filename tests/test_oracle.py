@@ -548,3 +548,128 @@ def test_planted_mistakes_are_caught(monkeypatch):
         return orig_z(F, Gm, sigma + 1e6) if s > 0 else (RA, RB, YL, YR)
     monkeypatch.setattr(O, "ordqz", farthest_first)
     assert _small_pencil_error() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# the Krylov-Arnoldi sequence against the correction operator in Kronecker form
+# ---------------------------------------------------------------------------
+
+def _kron_operators(A, B, V, L, MA, MB, T):
+    """Dense matrices acting on vec(C) (column-major) of an n-by-a block C:
+    the generalized Sylvester operator of eq. operator,
+        vec(L(C)) = (M_B^T kron P_L A P_V - M_A^T kron P_L B P_V) vec(C),
+    and the projected preconditioner of eq. prec_gen,
+        vec(T_L(C)) = (I kron P_V T P_L) vec(C),
+    with P_Y = I - Y Y^*; assembled from their definitions only."""
+    n = A.shape[0]
+    a = MA.shape[0]
+    PV = np.eye(n) - V @ V.conj().T
+    PL = np.eye(n) - L @ L.conj().T
+    Lk = np.kron(MB.T, PL @ A @ PV) - np.kron(MA.T, PL @ B @ PV)
+    Tk = np.kron(np.eye(a), PV @ T @ PL)
+    return Lk, Tk, PL
+
+
+def _vec(X):
+    return X.reshape(-1, order="F")
+
+
+def _unvec(x, n):
+    return x.reshape(n, -1, order="F")
+
+
+def _krylov_angles(A, B, sigma, T, V0, m, std, its=2):
+    """Largest principal angle, over the first iterations, between
+    col{W, S_1, .., S_l} produced by the oracle and the space the definitions
+    give: col{T_L F} for W, and col{W, S_1, .., S_{l-1}, T_L L(S_{l-1})} for
+    each further block (Algorithm 1 with the operators of eq. operator and
+    eq. prec_gen; Q is the left basis for B != I, V for B = I)."""
+    n = A.shape[0]
+    Bd = np.eye(n) if std else B
+    r = O.gplhr(sp.csr_matrix(A), None if std else sp.csr_matrix(B), sigma, V0.shape[1], V0,
+                lambda R: T @ R, m=m, tol=0.0, maxit=its, keep_trace=True)
+    worst = 0.0
+    for st in r.trace:
+        V, Q, MA, MB = st["V_in"], st["Q_in"], st["MA_in"], st["MB_in"]
+        L = V if std else Q
+        Lk, Tk, PL = _kron_operators(A, Bd, V, L, MA, MB, T)
+        F = -PL @ (A @ V @ MB - Bd @ V @ MA)
+        W, S = st["W"], st["S"]
+        worst = max(worst, np.max(sla.subspace_angles(W, _unvec(Tk @ _vec(F), n))))
+        blocks = [W]
+        for Sl in S:
+            nxt = _unvec(Tk @ (Lk @ _vec(blocks[-1])), n)
+            ref = np.hstack(blocks + [nxt])
+            got = np.hstack(blocks + [Sl])
+            worst = max(worst, np.max(sla.subspace_angles(got, ref)))
+            blocks.append(Sl)
+    return worst
+
+
+def _krylov_case(seed, std):
+    rng = np.random.default_rng(seed)
+    n, b = 36, 3
+    A = rand_c(rng, n, n) + 3 * np.eye(n)
+    B = np.eye(n) + 0.3 * rand_c(rng, n, n)
+    sigma = complex(rng.normal(), rng.normal())
+    C = A - sigma * (np.eye(n) if std else B)
+    # an inexact T ~ C^{-1}: the diagonal inverse, so that T_L L mixes the
+    # columns of its argument through M_A and M_B
+    T = np.diag(1.0 / np.diag(C))
+    return A, B, sigma, T, rand_c(rng, n, b)
+
+
+@pytest.mark.parametrize("seed,std", [(40, False), (41, True), (42, False)])
+def test_krylov_arnoldi_sequence_matches_the_correction_operator(seed, std):
+    A, B, sigma, T, V0 = _krylov_case(seed, std)
+    assert _krylov_angles(A, B, sigma, T, V0, m=2, std=std) < 1e-10
+
+
+def test_planted_mistakes_in_the_trial_subspace_are_caught(monkeypatch):
+    # the two slips a reading of the printed listing can make: M_A and M_B
+    # exchanged in the S recursion, and V taken as the left projector basis
+    # of a generalized problem
+    A, B, sigma, T, V0 = _krylov_case(40, False)
+    assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) < 1e-10
+    orig_op, orig_left = O.sylvester_operator, O.left_basis
+    monkeypatch.setattr(O, "sylvester_operator",
+                        lambda A_, Bm, V, L, MA, MB: orig_op(A_, Bm, V, L, MB, MA))
+    assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) > 1e-3
+    monkeypatch.setattr(O, "sylvester_operator", orig_op)
+    monkeypatch.setattr(O, "left_basis", lambda V, Q, standard: V)
+    assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) > 1e-3
+    monkeypatch.setattr(O, "left_basis", orig_left)
+    assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# 3-D generator against the closed form
+# ---------------------------------------------------------------------------
+
+def closed_form_3d(N, c):
+    mx, my, mz = (closed_form_1d(N, ci) for ci in c)
+    return (mx[:, None, None] + my[None, :, None] + mz[None, None, :]).ravel()
+
+
+@pytest.mark.parametrize("N,c", [(8, (20.0, 10.0, 5.0)), (9, (3.0, -7.0, 11.0))])
+def test_3d_stencil_matches_closed_form(N, c):
+    # the 3-D upwind operator is a Kronecker sum of three 1-D tridiagonal
+    # Toeplitz operators, so its spectrum is every sum of one eigenvalue of each
+    A = problems.convection_diffusion(N, c).to_scipy().toarray()
+    ev = np.linalg.eigvals(A)
+    ref = closed_form_3d(N, c)
+    assert np.max(np.abs(ev.imag)) < 1e-9 * np.max(np.abs(ref))
+    np.testing.assert_allclose(np.sort(ev.real), np.sort(ref), rtol=0, atol=1e-10 * np.max(ref))
+
+
+def test_3d_b_identity_nearest_values_64cube():
+    # the B = I variant of the 64^3 grid with sigma = 500 + 50i: the ten
+    # eigenvalues nearest sigma from the closed form; the spectrum is real,
+    # so nearest sigma means nearest Re(sigma) = 500
+    lam = closed_form_3d(64, (20.0, 10.0, 5.0))
+    near = nearest(lam, 500 + 50j, 11)
+    np.testing.assert_allclose(np.sort(near[:10]), np.sort([499.725, 502.078, 502.596, 504.345,
+                                                            493.894, 506.375, 491.713, 511.488,
+                                                            514.903, 483.605]), atol=5e-4)
+    d = np.abs(near - (500 + 50j))
+    assert 0.998 < d[9] / d[10] < 1.0
