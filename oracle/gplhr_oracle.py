@@ -263,30 +263,38 @@ def left_basis(V: np.ndarray, Q: np.ndarray, standard: bool) -> np.ndarray:
 
 
 def correction_rhs(A, Bmul, X: np.ndarray, L: np.ndarray, MA: np.ndarray,
-                   MB: np.ndarray) -> np.ndarray:
+                   MB: np.ndarray, project_left: bool = True) -> np.ndarray:
     """F of eq. operator: minus the projected residual of the Q-free Schur
     form (eq. gschur2), -(I - L L^*)(A X M_B - B X M_A).  With locking, M_A and
-    M_B are the columns of the active (trailing) pairs."""
-    return -projector(L)(A @ X @ MB - Bmul(X) @ MA)
+    M_B are the columns of the active (trailing) pairs.  project_left=False
+    leaves (I - L L^*) out, for the variant of Table 3 that omits the
+    projection performed before T."""
+    R = A @ X @ MB - Bmul(X) @ MA
+    return -(projector(L)(R) if project_left else R)
 
 
 def sylvester_operator(A, Bmul, V: np.ndarray, L: np.ndarray, MA: np.ndarray,
-                       MB: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+                       MB: np.ndarray, project_left: bool = True
+                       ) -> Callable[[np.ndarray], np.ndarray]:
     """The generalized Sylvester operator of eq. operator,
     C -> (P_L A P_V) C M_B - (P_L B P_V) C M_A, with P_Y = I - Y Y^*
-    (eq. sylvester for B != I, eq. sylvester_st with L = V for B = I)."""
+    (eq. sylvester for B != I, eq. sylvester_st with L = V for B = I).
+    project_left=False leaves P_L out (the variant of Table 3)."""
     PV, PL = projector(V), projector(L)
 
     def apply(C: np.ndarray) -> np.ndarray:
         Cp = PV(C)
-        return PL(A @ Cp @ MB - Bmul(Cp) @ MA)
+        Y = A @ Cp @ MB - Bmul(Cp) @ MA
+        return PL(Y) if project_left else Y
     return apply
 
 
 def projected_preconditioner(T: Callable, V: np.ndarray, L: np.ndarray,
                              right_projector: bool = True) -> Callable:
     """T_L of eq. prec_gen (eq. prec for B = I): (I - V V^*) T (I - L L^*).
-    Without the right projector it is (I - V V^*) T, the variant of Table 3."""
+    Without the right projector it is (I - V V^*) T: the variant of Table 3,
+    which together with project_left=False in the operator and right-hand
+    side applies T to the unprojected residual blocks."""
     PV, PL = projector(V), projector(L)
     if right_projector:
         return lambda X: PV(T(PL(X)))
@@ -429,8 +437,8 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
         # active pairs, L(C) = F with V^* C = 0 (eq. operator), and the
         # Krylov-Arnoldi sequence of T_L L from T_L F (Algorithm 1)
         L = left_basis(V, Q, std)
-        Lop = sylvester_operator(A, Bx, V, L, MA[q:, q:], MB[q:, q:])
-        F = correction_rhs(A, Bx, V, L, MA[:, q:], MB[:, q:])
+        Lop = sylvester_operator(A, Bx, V, L, MA[q:, q:], MB[q:, q:], proj_before_T)
+        F = correction_rhs(A, Bx, V, L, MA[:, q:], MB[:, q:], proj_before_T)
         TL = projected_preconditioner(precond, V, L, proj_before_T)
         W, S_list = krylov_arnoldi(TL, Lop, F, m)
         S = np.hstack(S_list)

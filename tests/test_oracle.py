@@ -633,7 +633,7 @@ def test_planted_mistakes_in_the_trial_subspace_are_caught(monkeypatch):
     assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) < 1e-10
     orig_op, orig_left = O.sylvester_operator, O.left_basis
     monkeypatch.setattr(O, "sylvester_operator",
-                        lambda A_, Bm, V, L, MA, MB: orig_op(A_, Bm, V, L, MB, MA))
+                        lambda A_, Bm, V, L, MA, MB, *rest: orig_op(A_, Bm, V, L, MB, MA, *rest))
     assert _krylov_angles(A, B, sigma, T, V0, m=2, std=False) > 1e-3
     monkeypatch.setattr(O, "sylvester_operator", orig_op)
     monkeypatch.setattr(O, "left_basis", lambda V, Q, standard: V)
