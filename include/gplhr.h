@@ -311,6 +311,23 @@ gplhr_status gplhr_csr_plane(int64_t n, const int32_t *row_ptr, const int32_t *c
 gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
                         const void *Y, int ldy, int by, void *G, void *hip_stream);
 
+/* The same G = X^H Y as gplhr_gram, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): it calls no allocating routine.  Its partial sums go to a
+ * 16 MiB array that the library keeps on each GPU until the process ends;
+ * the per-block partials of any bx, by <= 64 fit there (the number of row
+ * blocks is chosen so that they do).  Every call on one GPU shares that GPU's
+ * array, so calls that overlap in time on one GPU (concurrent streams or
+ * threads) race and give wrong results: serialise them.  Nothing in the array
+ * needs to start at zero; every call writes the partials it reads.
+ * Arguments, layout and errors as for gplhr_gram (ARG for widths outside
+ * 1..64, bad leading dimensions or NULL pointers; HIP when the device
+ * address of the array cannot be obtained).  The result agrees with
+ * gplhr_gram's to rounding (the partial sums may be grouped in fewer row
+ * blocks for the widest shapes). */
+gplhr_status gplhr_gram_noalloc(int dtype, int64_t n, const void *X, int ldx, int bx,
+                                const void *Y, int ldy, int by, void *G, void *hip_stream);
+
 /* Y = T R for the damped Jacobi preconditioner on C: T approximates C^{-1}
  * for C = A - sigma B, as Section 4 asks of the preconditioner that Algorithm
  * 2 applies in its steps 8 and 15.  From w_0 = 0, sweeps steps of

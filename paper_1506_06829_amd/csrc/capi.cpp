@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -371,6 +373,63 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
                                        static_cast<const float2 *>(Y), ldy, by, nullptr, part, cap,
                                        static_cast<double2 *>(G), bx);
         GPLHR_HIP_CHECK(hipFreeAsync(part, st));
+        return 0;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free Gram: its partial sums live in a file-scope device array.
+// ---------------------------------------------------------------------------
+// Each GPU the library runs on holds its own copy of this array until the
+// process ends.  In host code `scratch` names a host-side stand-in, so kernels
+// get the device address that hipGetSymbolAddress returns for the current
+// device (kept per device below), never the array's name.
+static constexpr size_t NOALLOC_SCRATCH_ENTRIES = (size_t)1 << 20;   // complex128, 16 MiB
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_ENTRIES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double2 *> g_scratch_ptr;   // device ordinal -> address of `scratch`
+
+// Device address of `scratch` on the current device; looked up once per device.
+double2 *scratch_on_current_device() {
+    int dev = -1;
+    GPLHR_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    GPLHR_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw gplhr::Error(-3, "gplhr_gram_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double2 *>(ptr);
+    return static_cast<double2 *>(ptr);
+}
+}  // namespace
+
+extern "C" {
+
+gplhr_status gplhr_gram_noalloc(int dtype, int64_t n, const void *X, int ldx, int bx,
+                                const void *Y, int ldy, int by, void *G, void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 1 || bx < 1 || by < 1 || bx > 64 || by > 64 || ldx < bx || ldy < by ||
+            (dtype != 0 && dtype != 1) || !X || !Y || !G)
+            throw gplhr::Error(-1, "gplhr_gram_noalloc: bad arguments");
+        // one block's real partial Gram takes 4 bx by doubles (2 bx by
+        // complex128 entries); the kernel uses as many blocks as fit
+        if ((size_t)2 * bx * by > NOALLOC_SCRATCH_ENTRIES)
+            throw gplhr::Error(-1, "gplhr_gram_noalloc: partial sums exceed the 16 MiB scratch");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        double2 *part = scratch_on_current_device();
+        if (dtype == 0)
+            gplhr::launch_gram<double2>(st, n, static_cast<const double2 *>(X), ldx, bx,
+                                        static_cast<const double2 *>(Y), ldy, by, nullptr, part,
+                                        NOALLOC_SCRATCH_ENTRIES, static_cast<double2 *>(G), bx);
+        else
+            gplhr::launch_gram<float2>(st, n, static_cast<const float2 *>(X), ldx, bx,
+                                       static_cast<const float2 *>(Y), ldy, by, nullptr, part,
+                                       NOALLOC_SCRATCH_ENTRIES, static_cast<double2 *>(G), bx);
         return 0;
     });
 }

@@ -69,7 +69,7 @@ EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
            "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram", "gplhr_jacobi",
-           "gplhr_block_update"]
+           "gplhr_block_update", "gplhr_gram_noalloc"]
 
 
 def lib():
@@ -112,6 +112,8 @@ def lib():
     L.gplhr_csr_plane.restype = i32
     L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
     L.gplhr_gram.restype = i32
+    L.gplhr_gram_noalloc.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
+    L.gplhr_gram_noalloc.restype = i32
     L.gplhr_block_update.argtypes = [i32, i64, vp, i32, i32, vp, i32, vp, i32, i32,
                                      ctypes.c_double, ctypes.c_double, vp]
     L.gplhr_block_update.restype = i32
@@ -350,6 +352,19 @@ def gram(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
     G = torch.empty((by, bx), dtype=torch.complex128, device=X.device)   # column-major bx x by
     _check(lib().gplhr_gram(dtype, X.shape[0], _ptr(X), X.stride(0), bx, _ptr(Y), Y.stride(0),
                             by, _ptr(G), _stream_ptr()))
+    return G.t()
+
+
+def gram_noalloc(X: torch.Tensor, Y: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
+    """G = X^H Y through the allocation-free entry point; the output G is
+    the caller's (by-by-bx complex128 storage, i.e. bx-by-by column-major),
+    returned as the bx-by-by view."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+    assert X.dtype == Y.dtype and X.stride(1) == 1 and Y.stride(1) == 1
+    bx, by = X.shape[1], Y.shape[1]
+    assert G.dtype == torch.complex128 and G.is_contiguous() and tuple(G.shape) == (by, bx)
+    _check(lib().gplhr_gram_noalloc(dtype, X.shape[0], _ptr(X), X.stride(0), bx, _ptr(Y),
+                                    Y.stride(0), by, _ptr(G), _stream_ptr()))
     return G.t()
 
 

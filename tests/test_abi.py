@@ -69,6 +69,11 @@ def test_argument_errors_without_device_work():
     assert b"gplhr_jacobi" in L.gplhr_last_error(None)
     assert L.gplhr_csr_plane(10, None, None, None, None) == -1
     assert L.gplhr_gram(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
+    # the allocation-free Gram rejects the same arguments before any device call
+    assert L.gplhr_gram_noalloc(0, 10, None, 4, 4, None, 4, 65, None, None) == -1
+    assert L.gplhr_gram_noalloc(0, 0, None, 4, 4, None, 4, 4, None, None) == -1
+    assert L.gplhr_gram_noalloc(2, 10, None, 4, 4, None, 4, 4, None, None) == -1
+    assert b"gplhr_gram_noalloc" in L.gplhr_last_error(None)
     for wx, wy in [(0, 4), (129, 4), (4, 0), (4, 49)]:
         assert L.gplhr_block_update(0, 10, None, 200, wx, None, 200, None, 200, wy,
                                     ctypes.c_double(0.0), ctypes.c_double(0.0), None) == -1
