@@ -186,7 +186,10 @@ void gplhr_default_options(gplhr_options *opt);
  * out    receives the handle (NULL on error).
  * Errors: ARG (sizes, malformed CSR, bad options), NUMERIC (non-finite
  * values), SINGULAR_SHIFT (zero on diag(C) with a diagonal-based T, or a
- * singular projected pencil), ALLOC, HIP. */
+ * singular projected pencil), BREAKDOWN (Schur form: V0 is numerically rank
+ * deficient, i.e. the Cholesky-QR of V0 meets a pivot of at most 64 eps of
+ * its diagonally scaled Gram matrix -- a repeated, zero or dependent column),
+ * ALLOC, HIP. */
 gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B,
                           double sigma_re, double sigma_im, int k, int block,
                           const gplhr_precond *T, const gplhr_options *opt,
@@ -197,7 +200,14 @@ gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B,
  * use opt.max_iter).  n_converged (may be NULL) receives the number of leading
  * pairs that meet tol; max_rel_resid (may be NULL) the largest relative
  * residual over the k leading pairs.  Returns OK when converged,
- * NOT_CONVERGED when the budget ran out; may be called again to continue. */
+ * NOT_CONVERGED when the budget ran out; may be called again to continue.
+ * Inside the iteration a vanishing Cholesky pivot (a block that lost rank,
+ * e.g. the residual columns of pairs that have converged exactly) is
+ * shifted, the second Cholesky-QR pass orthonormalises what is left, and
+ * gplhr_stats.breakdowns counts it; if the projected pencil of that
+ * iteration is then singular the call returns BREAKDOWN (SINGULAR_SHIFT
+ * when no pivot vanished).  Resume from saved Schur vectors by creating a
+ * handle with V0 = V. */
 gplhr_status gplhr_iterate(gplhr_t h, int max_iter, int *n_converged,
                            double *max_rel_resid);
 
@@ -212,6 +222,16 @@ gplhr_status gplhr_iterate(gplhr_t h, int max_iter, int *n_converged,
  * Synchronises the handle's stream. */
 gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB,
                              double *lambda, double *rel_resid);
+
+/* Residual norms ||A x_j - lambda_j B x_j|| / ||x_j|| of the k leading
+ * eigenpairs of the last convergence check (host k doubles), in the order of
+ * gplhr_get_schur's lambda (gplhr_get_eig's for GPLHR-EIG): the eigen-residual
+ * of Section 5.1 measured against ||x_j|| instead of ||A x_j||.  The x_j have
+ * unit norm (x_j = V z_j with orthonormal V and unit z_j; unit columns of X
+ * for GPLHR-EIG).  Computed in FP64 from the current blocks (complex64 ones
+ * during the complex64 phase).  Returns NOT_CONVERGED (results readable) when
+ * the handle has not converged, STATE before any check. */
+gplhr_status gplhr_get_residual_norms(gplhr_t h, double *resid);
 
 /* Copy the unit-norm Rayleigh-Ritz eigenvectors x_j = V z_j (device n-by-k
  * complex128 row-major, ld = k), in the order of gplhr_get_schur's lambda. */

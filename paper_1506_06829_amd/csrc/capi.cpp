@@ -141,6 +141,17 @@ gplhr_status gplhr_get_schur(gplhr_t h, void *V, void *Q, double *RA, double *RB
     });
 }
 
+gplhr_status gplhr_get_residual_norms(gplhr_t h, double *resid) {
+    if (!h || !resid) return GPLHR_ERR_ARG;
+    return guard(h, [&]() {
+        gplhr::Ctx &c = h->c;
+        if ((int)c.resid_h.size() < c.k) throw gplhr::Error(-8, "no iterate available");
+        // x_j = V z_j with orthonormal V and unit z_j, so ||x_j|| = 1
+        std::memcpy(resid, c.resid_h.data(), sizeof(double) * c.k);
+        return c.converged ? 0 : 1;
+    });
+}
+
 gplhr_status gplhr_get_eigvecs(gplhr_t h, void *X) {
     if (!h || !X) return GPLHR_ERR_ARG;
     return guard(h, [&]() {

@@ -128,6 +128,7 @@ struct Ctx {
     void copy_out(void *V, void *Q);
     void eigvecs(double2 *X);
 
+    int read_breakdowns();
     void tbegin(int cls);
     void tend(int cls);
     void tflush();
@@ -159,7 +160,7 @@ struct Ctx {
     template <typename T> void apply_gmres(T *dest, int ldd, int dcol, int w);
     template <typename T> void srr_and_update(int s_cur, int p_cols);
     void update_locking();
-    template <typename T> void init_from_Z(int w0);
+    template <typename T> void init_from_Z(int w0, bool check_rank);
     template <typename T> void init_eig();
     template <typename T> void eig_orthonormalise();
     template <typename T> void iterate_once();

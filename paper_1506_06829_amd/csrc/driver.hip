@@ -95,6 +95,14 @@ void Ctx::tflush() {
     }
 }
 
+// Vanishing Cholesky pivots counted on the device so far (waits for the stream).
+int Ctx::read_breakdowns() {
+    int *hs = reinterpret_cast<int *>(hpin);
+    GPLHR_HIP_CHECK(hipMemcpyAsync(hs, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+    GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+    return *hs;
+}
+
 template <> Work<double2> &Ctx::W<double2>() { return wd; }
 template <> Work<float2> &Ctx::W<float2>() { return wf; }
 
@@ -344,11 +352,21 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, fbase, (1 + 2 * ss) * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     tflush();
+    const int64_t breakdowns_before = n_breakdown;
     {
         int stv = 0;
         std::memcpy(&stv, hpin, sizeof(int));
         n_breakdown = stv;
     }
+    // a singular projected pencil after vanishing Cholesky pivots in this
+    // iteration comes from a block that lost rank, not from the shift
+    auto singular = [&]() {
+        if (n_breakdown > breakdowns_before)
+            return Error(-4, "orthonormalisation broke down: a block of the trial or test basis "
+                             "lost rank and the projected pencil is singular");
+        return Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
+                         "(Proposition 3.1)");
+    };
     // a9: ordered generalized Schur form on the host (FP64)
     auto t0 = std::chrono::steady_clock::now();
     Mat K(s_cur, s_cur), Gm(s_cur, s_cur);
@@ -366,9 +384,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         // nearest sigma; X = Z Ybar(:, 1:b), P = Z Ybar(:, b+1:b+p) (thick) or
         // P = [W S P] Ybar(b+1:s, 1:b) (LOBPCG-style, step 25)
         Mat Yb;
-        if (!small::harmonic_eig(K, Gm, nkeep, Yb))
-            throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
-                            "(Proposition 3.1)");
+        if (!small::harmonic_eig(K, Gm, nkeep, Yb)) throw singular();
         small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         int nc = Yb.c;
         cd *hc = reinterpret_cast<cd *>(hpin);
@@ -397,9 +413,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         return;
     }
     small::SrrResult r;
-    if (!small::harmonic_srr(K, Gm, sigma, b, nkeep, r))
-        throw Error(-5, "projected pencil is singular: sigma is numerically an eigenvalue "
-                        "(Proposition 3.1)");
+    if (!small::harmonic_srr(K, Gm, sigma, b, nkeep, r)) throw singular();
     small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     RA = r.RA; RB = r.RB; MA = r.MA; MB = r.MB;
     // coefficients: [Y_R | Y_P] (s_cur x nc), Y_L (s_cur x b), M1 = M_B, M2 = sigma M_B - M_A.
@@ -453,13 +467,28 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
 
 // Steps 1-4 of Algorithm 2 from Z(:, 0:w0) (V0, or [V P] when restarting in
 // another precision): orthonormalise, C Z, U = orth(C Z), ordered QZ, rotate.
+// check_rank: reject a numerically rank-deficient V0 (BREAKDOWN).
 template <typename T>
-void Ctx::init_from_Z(int w0) {
+void Ctx::init_from_Z(int w0, bool check_rank) {
     Work<T> &w = W<T>();
     const int ld = smax;
     if (defl_k)
         for (int pass = 0; pass < 2; ++pass) deflate_right<T>(w.Z, ld, 0, w0);
-    cholqr<T>(w.Z, ld, 0, w0, 2, nullptr, nullptr);
+    if (check_rank) {
+        // The starting block must have numerically full column rank: a
+        // vanishing pivot (at most 64 eps after diagonal scaling) in the first
+        // Cholesky-QR pass means a column depends on the others to about
+        // 1e-7 relative, and the shifted factor would fill it with rounding
+        // noise.  The counter is zero before the first pass of a handle.
+        cholqr<T>(w.Z, ld, 0, w0, 1, nullptr, nullptr);
+        const int pivots = read_breakdowns();
+        if (pivots > 0)
+            throw Error(-4, "the starting block is rank deficient: its Cholesky-QR met " +
+                                std::to_string(pivots) + " vanishing pivot(s)");
+        cholqr<T>(w.Z, ld, 0, w0, 1, nullptr, nullptr);
+    } else {
+        cholqr<T>(w.Z, ld, 0, w0, 2, nullptr, nullptr);
+    }
     for (int c = 0; c < w0; c += b) {
         const int wc = std::min(b, w0 - c);
         cprod<T>(w.Z + c, ld, w.CZ + c, ld, wc);
@@ -897,9 +926,9 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         launch_randn(st, n, b, opt.seed, wd.Z, smax);
     if (mixed) {
         launch_c128_to_c64(st, n, b, wd.Z, smax, wf.Z, smax);
-        if (eig) init_eig<float2>(); else init_from_Z<float2>(b);
+        if (eig) init_eig<float2>(); else init_from_Z<float2>(b, true);
     } else {
-        if (eig) init_eig<double2>(); else init_from_Z<double2>(b);
+        if (eig) init_eig<double2>(); else init_from_Z<double2>(b, true);
     }
     if (phase == 0) check<float2>(); else check<double2>();
     checked = true;
@@ -928,7 +957,7 @@ void Ctx::switch_to_fp64() {
         w0 = b + pw;
     }
     phase = 1;
-    init_from_Z<double2>(w0);
+    init_from_Z<double2>(w0, false);
     checked = false;
 }
 

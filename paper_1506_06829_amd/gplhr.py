@@ -69,7 +69,7 @@ EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
            "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram", "gplhr_jacobi",
-           "gplhr_block_update", "gplhr_gram_noalloc"]
+           "gplhr_block_update", "gplhr_gram_noalloc", "gplhr_get_residual_norms"]
 
 
 def lib():
@@ -91,6 +91,8 @@ def lib():
     L.gplhr_iterate.restype = i32
     L.gplhr_get_schur.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.gplhr_get_schur.restype = i32
+    L.gplhr_get_residual_norms.argtypes = [vp, vp]
+    L.gplhr_get_residual_norms.restype = i32
     L.gplhr_get_eigvecs.argtypes = [vp, vp]
     L.gplhr_get_eigvecs.restype = i32
     L.gplhr_get_eig.argtypes = [vp, vp, vp, vp, vp]
@@ -256,6 +258,12 @@ class Solver:
         if self.algorithm == "eig":
             return self.eig(want_vectors=False)["lam"]
         return self.schur(want_vectors=False)["lam"]
+
+    def residual_norms(self) -> np.ndarray:
+        """||A x_j - lambda_j B x_j|| / ||x_j|| of the k leading pairs (unit x_j)."""
+        out = np.zeros(self.k, dtype=np.float64)
+        _check(lib().gplhr_get_residual_norms(self.h, out.ctypes.data), self.h)
+        return out
 
     def eigvecs(self) -> torch.Tensor:
         X = torch.empty((self.n, self.k), dtype=torch.complex128, device="cuda")

@@ -5,6 +5,7 @@ pencil, Section 3.3), the ordered eigenvectors of Algorithm 3, and the Q-free
 factors of Theorem 2.2.  The C++ source is compiled with a small harness and
 checked against LAPACK (scipy) and the defining identities; the Q-free
 factors are also compared with the CPU oracle."""
+import os
 import subprocess
 from pathlib import Path
 
@@ -18,10 +19,20 @@ ROOT = Path(__file__).resolve().parents[1]
 CSRC = ROOT / "paper_1506_06829_amd" / "csrc"
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
-    exe = tmp_path_factory.mktemp("host") / "harness"
+# Host-only sanitizer build of small_dense.cpp (g++, no device code):
+# AddressSanitizer and UndefinedBehaviorSanitizer, any report fatal.
+SANITIZERS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+              "-fno-omit-frame-pointer", "-g"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def harness(request, tmp_path_factory):
+    """The harness built as the library builds small_dense.cpp, and again
+    with the host sanitizers: every check below runs on both builds."""
+    exe = tmp_path_factory.mktemp("host") / f"harness_{request.param}"
     flags = ["-O2", "-std=c++17", "-fcx-limited-range", f"-I{CSRC}"]
+    if request.param == "sanitized":
+        flags += SANITIZERS
     subprocess.run(["g++", *flags, str(ROOT / "tests" / "host_small_dense_harness.cpp"),
                     str(CSRC / "small_dense.cpp"), "-o", str(exe)], check=True)
     return exe
@@ -32,7 +43,11 @@ def fmt(M):
 
 
 def run(exe, text):
-    out = subprocess.run([str(exe)], input=text, capture_output=True, text=True, check=True).stdout
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    p = subprocess.run([str(exe)], input=text, capture_output=True, text=True, env=env)
+    assert p.returncode == 0, p.stderr[-4000:]
+    out = p.stdout
     lines = out.splitlines()
     ok = lines[0].split()[1] == "1"
     res, i = {}, 1
