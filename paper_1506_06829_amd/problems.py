@@ -208,6 +208,10 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
         slowly), n=262144, B=diag U[1,2], sigma=n/2+0.3i, k=b=10, T = 2 block
         GMRES steps right-preconditioned by 3 Jacobi sweeps (omega=0.7), complex128
     d2m d2 in mixed precision
+    c1g c1 with the stronger preconditioner of Section 4 -- T = 8 block GMRES
+        steps right-preconditioned by 3 Jacobi sweeps (omega=0.7) -- and a
+        block of 8 columns for the k=4 wanted pairs (diag(C) is constant on
+        c1, so its diagonal preconditioner is a scalar)
 
     ``scale`` overrides the grid size N (stencils) or n (random pencil) to give
     a smaller instance of the same family.
@@ -216,6 +220,10 @@ def config(name: str, scale: Optional[int] = None) -> Problem:
         N = scale or 32
         return _with_v0(Problem("c1", convection_diffusion(N, (10.0, 10.0)), None, 200.0 + 0j,
                                 4, 4, "diag"))
+    if name == "c1g":
+        N = scale or 32
+        return _with_v0(Problem("c1g", convection_diffusion(N, (10.0, 10.0)), None, 200.0 + 0j,
+                                4, 8, "gmres", 3, 0.7, steps=8, inner="jacobi"))
     if name in ("c2", "c3"):
         N = scale or 64
         A = convection_diffusion(N, (20.0, 10.0, 5.0))

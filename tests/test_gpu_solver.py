@@ -538,3 +538,152 @@ def test_workspace_reuse_gives_identical_solves(device):
     other.iterate(2)
     other.close()
     assert np.array_equal(lam1, lam3) and np.array_equal(V1, V3)
+
+
+@pytest.mark.parametrize("kind", ["duplicate", "zero"])
+def test_rank_deficient_start_block_is_a_breakdown(device, kind):
+    # a starting block with a repeated or a zero column has no orthonormal
+    # basis of its span with as many columns: its Cholesky-QR meets a
+    # vanishing pivot, and create reports BREAKDOWN instead of iterating on a
+    # basis padded with rounding noise
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    p = problems.config("d1", 3000)
+    V0 = p.V0.copy()
+    if kind == "duplicate":
+        V0[:, 3] = V0[:, 1]
+    else:
+        V0[:, 5] = 0.0
+    A, B = G.DeviceCsr.from_host(p.A), G.DeviceCsr.from_host(p.B)
+    with pytest.raises(G.GplhrError) as e:
+        G.Solver(A, B, p.sigma, p.k, p.block, precond="diag",
+                 V0=torch.as_tensor(V0).to("cuda"))
+    assert e.value.status == -4
+    assert "rank deficient" in str(e.value)
+    # a block with nearly (1e-5) dependent columns is still a valid start
+    V0 = p.V0.copy()
+    V0[:, 3] = V0[:, 1] + 1e-5 * V0[:, 3]
+    s = G.Solver(A, B, p.sigma, p.k, p.block, precond="diag", max_iter=100,
+                 V0=torch.as_tensor(V0).to("cuda"))
+    st, _, res = s.iterate()
+    lam = s.lam()
+    s.close()
+    assert st == 0 and res <= 1e-10
+    ref = O.solve_problem(p, tol=1e-10, maxit=100)
+    assert match_err(lam[:p.k], ref.lam[:p.k]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resume_from_converged_schur_vectors(device, precision):
+    # checkpoint / resume: a new handle started from the converged V of an
+    # earlier one reconverges in at most one iteration to the same eigenvalues
+    import torch
+    p = problems.config("d1", 3000)
+    s1, A, B = gpu_solver(p, precision=precision, max_iter=100)
+    assert s1.iterate()[0] == 0
+    out1 = s1.schur()
+    s1.close()
+    from paper_1506_06829_amd import gplhr as G
+    # the resumed run is FP64: the saved V carries the first run's accuracy
+    s2 = G.Solver(A, B, p.sigma, p.k, p.block, precond="diag", precision="fp64",
+                  max_iter=100, V0=out1["V"].contiguous())
+    st, nconv, res = s2.iterate()
+    stats = s2.stats()
+    lam2 = s2.lam()
+    s2.close()
+    assert st == 0 and nconv == p.k and res <= 1e-10
+    assert stats["iterations"] <= 1
+    assert match_err(lam2, out1["lam"]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_residual_norms_match_definition(device, precision):
+    # ||A x - lambda B x|| / ||x|| of the exported Rayleigh-Ritz pairs,
+    # recomputed on the CPU from the GPU's eigenvectors
+    p = problems.config("d1", 3000)
+    s, _, _ = gpu_solver(p, precision=precision, tol=0.0, max_iter=3, switch_tol=0.0,
+                         stall_window=10**6)
+    s.iterate(3)
+    lam = s.schur(want_vectors=False)["lam"]
+    X = s.eigvecs().cpu().numpy()
+    got = s.residual_norms()
+    s.close()
+    A, B = p.A.to_scipy(), p.B.to_scipy()
+    ref = np.linalg.norm(A @ X - (B @ X) * lam[None, :], axis=0) / np.linalg.norm(X, axis=0)
+    np.testing.assert_allclose(got, ref, rtol=1e-6 if precision == "fp64" else 1e-2)
+
+
+C1_CLOSED_FORM = [189.2477651, 189.2477651, 232.95958078, 232.95958078]
+
+
+def _c1_closed_form():
+    """The four eigenvalues of the c1 stencil nearest 200, from the closed
+    form of the 2-D upwind operator (sums of two 1-D Toeplitz spectra)."""
+    N, c = 32, 10.0
+    h = 1.0 / (N + 1)
+    j = np.arange(1, N + 1)
+    mu = (2 + c * h) / h**2 - (2 / h**2) * np.sqrt(1 + c * h) * np.cos(j * np.pi * h)
+    lam = (mu[:, None] + mu[None, :]).ravel()
+    return nearest(lam, 200.0, 4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_converges_to_the_closed_form(device, precision):
+    # c1 (2-D upwind, N = 32, sigma = 200, k = 4) with the stronger T of
+    # Section 4 and an 8-column block: the four eigenvalues (two double ones)
+    # are the closed-form values and the oracle's.  At a 1e-10 residual a
+    # double eigenvalue is only within about kappa * 1e-10 (kappa up to 45 on
+    # c1), so both solvers go to 1e-13, near the FP64 floor.
+    p = problems.config("c1g")
+    p.tol = 1e-13
+    ref_cf = _c1_closed_form()
+    np.testing.assert_allclose(np.sort(ref_cf.real), C1_CLOSED_FORM, rtol=1e-9)
+    s, _, _ = gpu_solver(p, precision=precision, max_iter=1500, tol=1e-13)
+    st, nconv, res = s.iterate()
+    lam = s.lam()
+    stats = s.stats()
+    s.close()
+    print(f"c1g {precision}: status {st}, {stats['iterations']} iterations, residual {res:.2e}",
+          flush=True)
+    assert st == 0 and nconv == p.k and res <= 1e-13
+    assert match_err(lam[:p.k], ref_cf) < 1e-10
+    ref = O.solve_problem(p, tol=1e-13, maxit=1500)
+    assert ref.converged
+    assert match_err(lam[:p.k], ref.lam[:p.k]) < 1e-10
+
+
+def test_trajectory_parity_full_size_64cube_mixed(device):
+    # the named 64^3 pencil in mixed precision (complex64 bulk, FP64 Grams,
+    # projected step and residuals): two iterations against the FP64 oracle
+    # at the complex64 tolerance
+    p = problems.config("c3")
+    its = 2
+    gpu = gpu_trajectory(p, its, precision="mixed", switch_tol=0.0, stall_window=10**6)
+    ref = O.solve_problem(p, tol=0.0, maxit=its).lam_history
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        err = match_err(a[:p.k], b[:p.k])
+        print(f"c3 64^3 mixed iteration {i}: eigenvalue rel. difference vs FP64 oracle {err:.2e}",
+              flush=True)
+        assert err < MIXED_TRAJ_TOL, i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trajectory_parity_full_size_160cube(device, precision):
+    # the largest workload (n = 4096000, k = b = 16, Jacobi-3): the
+    # Rayleigh-Ritz eigenvalues after set-up and after one iteration against
+    # the FP64 oracle run on the host at full size
+    p = problems.config("c5")
+    its = 1
+    gpu = gpu_trajectory(p, its, precision=precision, switch_tol=0.0, stall_window=10**6)
+    ref = _c5_oracle_trajectory(its)
+    tol = FP64_TRAJ_TOL if precision == "fp64" else MIXED_TRAJ_TOL
+    for i, (a, b) in enumerate(zip(gpu, ref)):
+        err = match_err(a[:p.k], b[:p.k])
+        print(f"c5 160^3 {precision} iteration {i}: eigenvalue rel. difference vs FP64 oracle "
+              f"{err:.2e}", flush=True)
+        assert err < tol, i
+
+
+@functools.lru_cache(maxsize=None)
+def _c5_oracle_trajectory(its):
+    return tuple(O.solve_problem(problems.config("c5"), tol=0.0, maxit=its).lam_history)
