@@ -331,6 +331,16 @@ gplhr_status gplhr_csr_plane(int64_t n, const int32_t *row_ptr, const int32_t *c
 gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
                         const void *Y, int ldy, int by, void *G, void *hip_stream);
 
+/* Y(:, 0:w) = X(:, 0:w) for row-major device blocks, as a hand-written
+ * streaming kernel (16-byte vector loads and stores, four in flight per
+ * thread): the copy-out of the Schur vectors V, Q (Algorithm 2 output) is such
+ * a block copy, and timing it on large blocks gives the HBM bandwidth a
+ * kernel that reads and writes each byte once attains.  dtype 0: complex128;
+ * 1: complex64 with even w and leading dimensions.  X and Y 16-byte aligned,
+ * not overlapping.  Returns ARG otherwise. */
+gplhr_status gplhr_block_copy(int dtype, int64_t n, const void *X, int ldx, void *Y, int ldy, int w,
+                              void *hip_stream);
+
 /* The same G = X^H Y as gplhr_gram, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): it calls no allocating routine.  Its partial sums go to a

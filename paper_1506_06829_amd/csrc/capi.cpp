@@ -421,6 +421,26 @@ double2 *scratch_on_current_device() {
 
 extern "C" {
 
+gplhr_status gplhr_block_copy(int dtype, int64_t n, const void *X, int ldx, void *Y, int ldy, int w,
+                              void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 0 || w < 1 || ldx < w || ldy < w || (dtype != 0 && dtype != 1))
+            throw gplhr::Error(-1, "gplhr_block_copy: bad arguments");
+        if (n == 0) return 0;
+        if (!X || !Y) throw gplhr::Error(-1, "gplhr_block_copy: null pointer");
+        const uintptr_t al = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y);
+        // 16-byte vectors: whole complex128 entries, or complex64 pairs
+        if (dtype == 1 && (w % 2 != 0 || ldx % 2 != 0 || ldy % 2 != 0 || al % 16 != 0))
+            throw gplhr::Error(-1, "gplhr_block_copy: complex64 blocks need even widths, even "
+                                   "leading dimensions and 16-byte alignment");
+        if (dtype == 0 && al % 16 != 0) throw gplhr::Error(-1, "gplhr_block_copy: misaligned block");
+        const int per = dtype == 0 ? 1 : 2;   // complex entries per vector
+        gplhr::launch_block_copy(static_cast<hipStream_t>(hip_stream), n, w / per, X, ldx / per, Y,
+                                 ldy / per);
+        return 0;
+    });
+}
+
 gplhr_status gplhr_gram_noalloc(int dtype, int64_t n, const void *X, int ldx, int bx,
                                 const void *Y, int ldy, int by, void *G, void *hip_stream) {
     return guard(nullptr, [&]() {

@@ -136,7 +136,7 @@ struct Ctx {
     template <typename T> Work<T> &W();
     template <typename T>
     void gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
-              double2 *out);
+              double2 *out, bool f32 = false);
     template <typename T>
     void update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1, int nterms,
                 const UpdTerm<T> *terms, const T *add = nullptr, int ldadd = 0);
@@ -146,6 +146,8 @@ struct Ctx {
                  const T *ymir2 = nullptr);
     template <typename T>
     void cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2);
+    template <typename T>
+    void proj_orth(T *X, int ld, int ycol, int wy, int xcol, int w, int passes);
     template <typename T>
     void spmm_c(const T *X, int ldx, T *Y, int ldy, int w, int mode, const T *Rhs, int ldr);
     template <typename T>

@@ -111,9 +111,9 @@ template <> Work<float2> &Ctx::W<float2>() { return wf; }
 // ---------------------------------------------------------------------------
 template <typename T>
 void Ctx::gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
-               double2 *out) {
+               double2 *out, bool f32) {
     tbegin(T_GRAM);
-    launch_gram<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_CAP, out, bx);
+    launch_gram<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_CAP, out, bx, f32);
     tend(T_GRAM);
 }
 
@@ -165,6 +165,26 @@ void Ctx::cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2) {
             t.in = mir2;
             update<T>(mir2, ld, w, col, w, 0, false, 1, &t);
         }
+    }
+}
+
+// X(:, xcol:xcol+w) <- orth((I - Y Y^H) X) for Y = X(:, ycol:ycol+wy), the
+// orthonormal columns just before the block (ycol + wy = xcol; wy may be 0).
+// Each pass is one Gram [Y X]^H X, the Cholesky factor of the projected
+// block's Gram X^H X - (Y^H X)^H (Y^H X), and one row-local update
+// X <- X Rinv + Y Cy with Cy = -(Y^H X) Rinv; a second pass restores what
+// the first loses to cancellation (two passes equal block Gram-Schmidt twice
+// followed by Cholesky-QR twice, to rounding).  A pass whose projection
+// cancels almost all of a column only projects (see launch_chol_proj).
+template <typename T>
+void Ctx::proj_orth(T *X, int ld, int ycol, int wy, int xcol, int w, int passes) {
+    for (int p = 0; p < passes; ++p) {
+        gram<T>(X + ycol, ld, wy + w, X + xcol, ld, w, nullptr, g0);
+        launch_chol_proj(st, wy, w, g0, rinv, g1, dstatus, p + 1 < passes);
+        UpdTerm<T> t[2];
+        t[0].in = X; t[0].ld = ld; t[0].col = xcol; t[0].w = w; t[0].M = rinv; t[0].ldm = w;
+        t[1].in = X; t[1].ld = ld; t[1].col = ycol; t[1].w = wy; t[1].M = g1; t[1].ldm = wy;
+        update<T>(X, ld, w, xcol, w, 0, false, wy > 0 ? 2 : 1, t);
     }
 }
 
@@ -347,8 +367,10 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     // F2 follows F1 in one buffer, so both come back in one copy
     const size_t ss = (size_t)s_cur * s_cur;
     double2 *F2 = F1 + ss;
-    gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
-    gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
+    // (in the complex64 phase on the FP32 MFMA with FP64 accumulation across
+    // rows, the precision of its operands; Section 3.3's pencil)
+    gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1, true);
+    gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2, true);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, fbase, (1 + 2 * ss) * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     tflush();
@@ -580,11 +602,9 @@ void Ctx::iterate_once() {
         update<T>(w.R, b, a, 0, a, 0, false, 2, t);
         if (opt.proj_before_T) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
         apply_T<T>(Z, ld, dst, a);
-        for (int pass = 0; pass < 2; ++pass) {
-            if (defl_k) deflate_right<T>(Z, ld, dst, a);
-            project<T>(Z, ld, dst, a, Z, ld, 0, dst);
-        }
-        cholqr<T>(Z, ld, dst, a, 2, nullptr, nullptr);
+        if (defl_k)
+            for (int pass = 0; pass < 2; ++pass) deflate_right<T>(Z, ld, dst, a);
+        proj_orth<T>(Z, ld, 0, dst, dst, a, 2);
         cprod<T>(Z + dst, ld, CZ + dst, ld, a);
         bprod<T>(Z + dst, ld, BZ + dst, ld, a);
     };
@@ -601,24 +621,32 @@ void Ctx::iterate_once() {
             // (row-local, so overlapping column ranges are safe)
             update<T>(Z, ld, pa, pos, pa, 0, false, 0, nullptr, Z + offPs, ld);
         }
-        for (int pass = 0; pass < 2; ++pass) project<T>(Z, ld, pos, pa, Z, ld, 0, pos);
-        cholqr<T>(Z, ld, pos, pa, 2, nullptr, nullptr);
+        // the LOBPCG-style P (the previous V) lies almost inside span [V W S]
+        // once V converges: its first pass is a plain projection, so it takes
+        // a third one
+        proj_orth<T>(Z, ld, 0, pos, pos, pa, opt.p_mode == GPLHR_P_LOBPCG ? 3 : 2);
         // C P (and B P) by fresh sparse products: one SpMM moves fewer bytes
         // than mirroring the four updates above onto C Z
         cprod<T>(Z + pos, ld, CZ + pos, ld, pa);
         bprod<T>(Z + pos, ld, BZ + pos, ld, pa);
     }
-    // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])]
+    // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])].  First pass from
+    // X = C [W S P]: the Grams Q^H X and X^H X into one (b + wq)-by-wq array,
+    // the projected Cholesky factor, and U(:, b:) = X Rinv + Q Cy; the second
+    // pass on U itself.
     const int wq = s_cur - b;
-    gram<T>(U, ld, b, CZ + b, ld, wq, nullptr, g0);
     {
-        UpdTerm<T> t;
-        t.in = U; t.ld = ld; t.col = 0; t.w = b; t.M = g0; t.ldm = b;
-        t.alpha = make_double2(-1.0, 0.0);
-        update<T>(U, ld, wq, b, wq, 0, false, 1, &t, CZ + b, ld);
+        tbegin(T_GRAM);
+        launch_gram<T>(st, n, U, ld, b, CZ + b, ld, wq, nullptr, part, PART_CAP, g0, b + wq);
+        launch_gram<T>(st, n, CZ + b, ld, wq, CZ + b, ld, wq, nullptr, part, PART_CAP, g0 + b, b + wq);
+        tend(T_GRAM);
+        launch_chol_proj(st, b, wq, g0, rinv, g1, dstatus, true);
+        UpdTerm<T> t[2];
+        t[0].in = CZ; t[0].ld = ld; t[0].col = b; t[0].w = wq; t[0].M = rinv; t[0].ldm = wq;
+        t[1].in = U; t[1].ld = ld; t[1].col = 0; t[1].w = b; t[1].M = g1; t[1].ldm = b;
+        update<T>(U, ld, wq, b, wq, 0, false, 2, t);
     }
-    project<T>(U, ld, b, wq, U, ld, 0, b);
-    cholqr<T>(U, ld, b, wq, 2, nullptr, nullptr);
+    proj_orth<T>(U, ld, 0, b, b, wq, 1);
     // steps 25-31
     srr_and_update<T>(s_cur, opt.p_mode == GPLHR_P_NONE ? 0 : a);
     ++n_iter;
@@ -1049,7 +1077,7 @@ template void Ctx::update<double2>(double2 *, int, int, int, int, int, bool, int
 }  // namespace gplhr
 namespace gplhr {
 template void Ctx::gram<double2>(const double2 *, int, int, const double2 *, int, int,
-                                 const double2 *, double2 *);
+                                 const double2 *, double2 *, bool);
 template void Ctx::gram<float2>(const float2 *, int, int, const float2 *, int, int, const float2 *,
-                                double2 *);
+                                double2 *, bool);
 }  // namespace gplhr

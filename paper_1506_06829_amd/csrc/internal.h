@@ -53,10 +53,13 @@ int spmm_plane(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci);
 
 // G = X^H diag(yscale) Y (bx-by-by, FP64 accumulation, fixed reduction order)
 // written column-major with leading dimension ldo.  yscale (complex per row)
-// may be null.  `part` is scratch of part_cap complex128 entries.
+// may be null.  `part` is scratch of part_cap complex128 entries.  f32 (for
+// complex64 operands; ignored for complex128): products on the FP32 MFMA,
+// summed in FP32 over a few rows per wave and in FP64 beyond that.
 template <typename T>
 void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
-                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo);
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo,
+                 bool f32 = false);
 
 // out[p + q*ldo] = sum_blk part[(p + q*bx) * nblk + blk]  (fixed order)
 void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,
@@ -92,11 +95,28 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
 // shift and increments status[0].
 void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status,
                       double2 *Rout = nullptr);
+// Projected Cholesky-QR factor: G is [Y X]^H X ((wy + w)-by-w, column-major,
+// leading dimension wy + w) for Y with orthonormal columns; with
+// P = X^H X - (Y^H X)^H (Y^H X), the Gram of X - Y (Y^H X), writes Rinv
+// (w-by-w) with P = R^H R as launch_chol_rinv does, and Cy = -(Y^H X) Rinv
+// (wy-by-w, leading dimension wy), so that Y Cy + X Rinv is orthonormal and
+// orthogonal to Y.  With guard set, when the projection cancels more than
+// 1e-8 of a column's squared norm (X nearly inside span Y) the factor would be
+// unreliable: Rinv is then the identity and Cy = -(Y^H X), a plain projection,
+// and the next pass normalises (the last pass of a sequence runs without the
+// guard).  w <= 48, wy <= 48, wy + w <= 64.
+void launch_chol_proj(hipStream_t st, int wy, int w, const double2 *G, double2 *Rinv, double2 *Cy,
+                      int *status, bool guard);
 
 // Out(:, 0:w) = rowscale .* In(:, 0:w)  (rowscale complex per row; null = copy)
 template <typename T>
 void launch_scale_rows(hipStream_t st, int64_t n, int w, const T *in, int ldi, const T *rowscale,
                        T *out, int ldo);
+
+// Y = X for row-major blocks of wv 16-byte vectors per row (leading
+// dimensions in vectors), a streaming copy kernel.
+void launch_block_copy(hipStream_t st, int64_t n, int wv, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy);
 
 // Convert between precisions (w columns).
 void launch_c128_to_c64(hipStream_t st, int64_t n, int w, const double2 *in, int ldi, float2 *out,

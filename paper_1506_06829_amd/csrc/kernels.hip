@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -98,6 +99,26 @@ __device__ __forceinline__ void store_vec(T *p, const T (&x)[CPL]) {
             *reinterpret_cast<float4 *>(p + c) = make_float4(x[c].x, x[c].y, x[c + 1].x, x[c + 1].y);
     }
 }
+// The same with non-temporal stores (streamed past the caches): for outputs
+// too large to stay in the Infinity Cache until they are read again.
+template <typename T, int CPL>
+__device__ __forceinline__ void store_vec_nt(T *p, const T (&x)[CPL]) {
+    typedef float f2n __attribute__((ext_vector_type(2)));
+    typedef float f4n __attribute__((ext_vector_type(4)));
+    typedef double d2n __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 16) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            __builtin_nontemporal_store(d2n{x[c].x, x[c].y}, reinterpret_cast<d2n *>(p + c));
+    } else if constexpr (CPL == 1) {
+        __builtin_nontemporal_store(f2n{x[0].x, x[0].y}, reinterpret_cast<f2n *>(p));
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPL; c += 2)
+            __builtin_nontemporal_store(f4n{x[c].x, x[c].y, x[c + 1].x, x[c + 1].y},
+                                        reinterpret_cast<f4n *>(p + c));
+    }
+}
 
 template <typename T>
 struct SpmmArgs {
@@ -121,13 +142,29 @@ struct SpmmArgs {
     int sp;         // >0: plane-slab row schedule with planes of sp rows
     int ss;         // slab: sp / 8 rows of each plane
     int sperx;      // rows per XCD: n / 8
+    int nt;         // 1: non-temporal stores of Y
 };
 
 // MODE 0: Y = C X; MODE 1: the damped Jacobi sweep (compile-time, so the plain
 // product carries no epilogue registers).  BATCH entries of a row have their
 // block-row gathers in flight together.
+//
+// Index/value stream through LDS: when the rows of a workgroup are
+// consecutive rows of the matrix (always in natural order; in the plane-slab
+// order unless the workgroup straddles a slab) and their entries fit in
+// SPMM_STAGE entries, the workgroup first copies its row pointers and then
+// its whole contiguous segment of column indices and values into LDS with
+// coalesced loads; each lane group then reads its row's entries from LDS.
+// Otherwise every lane group reads its row's entries from global memory.
+// Both paths take a row's entries in the same order, so the results are the
+// same bit for bit.
+constexpr int SPMM_STAGE = 1024;
+
 template <typename T, int CPL, int MODE, int BATCH>
 __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
+    __shared__ int32_t s_ci[SPMM_STAGE];
+    __shared__ T s_val[SPMM_STAGE];
+    __shared__ int32_t s_rp[257];
     int blk = blockIdx.x;
     if (a.per_xcd > 0) {
         blk = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
@@ -137,15 +174,38 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     const int wave = threadIdx.x >> 6;
     const int rw = lane / a.lpr;
     const int cl = lane - rw * a.lpr;
-    const int64_t pos = ((int64_t)blk * 4 + wave) * a.rpw + rw;
-    const int c0 = cl * CPL;
-    if (rw >= a.rpw || pos >= a.n || c0 >= a.b) return;
-    int64_t row = pos;
-    if (a.sp > 0) {
+    auto row_of = [&](int64_t pos) -> int64_t {
+        if (a.sp <= 0) return pos;
         // XCD x takes slab x of every plane, planes in order (n < 2^31)
         const int p = (int)pos, x = p / a.sperx, r = p - x * a.sperx, z = r / a.ss;
-        row = (int64_t)z * a.sp + (int64_t)x * a.ss + (r - z * a.ss);
+        return (int64_t)z * a.sp + (int64_t)x * a.ss + (r - z * a.ss);
+    };
+    // the workgroup's rows: positions pos0 .. pos0 + nr - 1
+    const int rows_blk = 4 * a.rpw;
+    const int64_t pos0 = (int64_t)blk * rows_blk;
+    const int nr = (int)min((int64_t)rows_blk, a.n - pos0);
+    const int64_t row0 = row_of(pos0);
+    const bool contiguous = (row_of(pos0 + nr - 1) - row0 == nr - 1);
+    bool staged = false;
+    int e0 = 0;
+    if (contiguous) {
+        for (int t = threadIdx.x; t <= nr; t += 256) s_rp[t] = a.rp[row0 + t];
+        __syncthreads();
+        e0 = s_rp[0];
+        const int ne = s_rp[nr] - e0;
+        staged = ne <= SPMM_STAGE;   // the same for every thread of the workgroup
+        if (staged) {
+            for (int e = threadIdx.x; e < ne; e += 256) {
+                s_ci[e] = a.ci[e0 + e];
+                s_val[e] = a.val[e0 + e];
+            }
+            __syncthreads();
+        }
     }
+    const int r = wave * a.rpw + rw;
+    const int c0 = cl * CPL;
+    if (rw >= a.rpw || r >= nr || c0 >= a.b) return;
+    const int64_t row = contiguous ? row0 + r : row_of(pos0 + r);
 
     // epilogue operands first, so their latency overlaps the gather
     T xo[CPL], rh[CPL], w = czero<T>();
@@ -157,19 +217,10 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
     T acc[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) acc[u] = czero<T>();
-    const int p0 = a.rp[row], p1 = a.rp[row + 1];
     const T *__restrict__ Xc = a.X + c0;
     // whole batches of the row's index/value stream are in flight before the
     // dependent block-row gathers are issued
-    for (int p = p0; p < p1; p += BATCH) {
-        int j[BATCH];
-        T v[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            const bool ok = p + u < p1;
-            j[u] = ok ? a.ci[p + u] : -1;
-            v[u] = ok ? a.val[p + u] : czero<T>();
-        }
+    auto gather = [&](int j[BATCH], T v[BATCH]) {
         T x[BATCH][CPL];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
@@ -184,6 +235,33 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
         for (int u = 0; u < BATCH; ++u)
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cfma(acc[c], v[u], x[u][c]);
+    };
+    if (staged) {
+        const int p0 = s_rp[r] - e0, p1 = s_rp[r + 1] - e0;
+        for (int p = p0; p < p1; p += BATCH) {
+            int j[BATCH];
+            T v[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const bool ok = p + u < p1;
+                j[u] = ok ? s_ci[p + u] : -1;
+                v[u] = ok ? s_val[p + u] : czero<T>();
+            }
+            gather(j, v);
+        }
+    } else {
+        const int p0 = a.rp[row], p1 = a.rp[row + 1];
+        for (int p = p0; p < p1; p += BATCH) {
+            int j[BATCH];
+            T v[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const bool ok = p + u < p1;
+                j[u] = ok ? a.ci[p + u] : -1;
+                v[u] = ok ? a.val[p + u] : czero<T>();
+            }
+            gather(j, v);
+        }
     }
     T out[CPL];
     if constexpr (MODE == 0) {
@@ -196,7 +274,8 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
             cfma(out[c], w, csub(rh[c], acc[c]));
         }
     }
-    store_vec<T, CPL>(a.Y + row * a.ldy + c0, out);
+    if (a.nt) store_vec_nt<T, CPL>(a.Y + row * a.ldy + c0, out);
+    else store_vec<T, CPL>(a.Y + row * a.ldy + c0, out);
 }
 
 // Row schedule.  Without a plane, rows run in natural order and blocks are
@@ -246,7 +325,10 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
     if (n <= 0) return;
     if (plane < 0 || (plane > 0 && (n % plane != 0 || plane % 8 != 0)))
         throw Error(-1, "spmm: the plane must divide n and be a multiple of 8");
-    SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0, 0, 0, 0};
+    SpmmArgs<T> a{n, rp, ci, val, X, ldx, Y, ldy, b, mode, Rhs, ldr, dw, 0, 0, 0, 0, 0, 0, 0, 0};
+    // an output block larger than the 256 MB Infinity Cache cannot stay there
+    // until it is read again: stream it past the caches
+    a.nt = ((double)n * b * sizeof(T) > 256.0 * 1024 * 1024) ? 1 : 0;
     // lanes move 32 bytes of the block row: 4 complex64 or 2 complex128 values
     const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
                             (mode == 1 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
@@ -360,6 +442,7 @@ struct GramMArgs {
 };
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <typename T> struct RealOf;
 template <> struct RealOf<double2> { using R = double; };
@@ -369,10 +452,16 @@ constexpr int GM_PF = 4;   // K steps in flight per wave
 
 // OCC: waves per SIMD the register allocation must leave room for (1: the
 // compiler's choice; 2: at most 256 VGPRs + AGPRs per lane).
-template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
+// F32 (complex64 operands only): the products run on the FP32 MFMA
+// (v_mfma_f32_16x16x4f32) and accumulate in FP32 over the PF K steps of one
+// round (4 PF rows per wave), after which the FP32 tile is added to an FP64
+// accumulator; everything across rounds, waves and blocks is FP64.
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1, bool F32 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, 8)))
 void gram_mfma_kernel(GramMArgs<T> a) {
     using R = typename RealOf<T>::R;
+    static_assert(!F32 || sizeof(T) == 8, "the FP32 MFMA build is for complex64 operands");
+    using OpR = typename std::conditional<F32, float, double>::type;
     __shared__ double red[2 * MTC * NTC * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = wave % a.G, h = wave / a.G;
@@ -381,10 +470,17 @@ void gram_mfma_kernel(GramMArgs<T> a) {
     const int nbx = 2 * a.bx, nby = 2 * a.by;
     const int nt0 = g * a.NTg;
     d4v acc[MTC][NTC];
+    f4v acc32[F32 ? MTC : 1][F32 ? NTC : 1];
 #pragma unroll
     for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
         for (int t = 0; t < NTC; ++t) acc[mt][t] = d4v{0.0, 0.0, 0.0, 0.0};
+    if constexpr (F32) {
+#pragma unroll
+        for (int mt = 0; mt < MTC; ++mt)
+#pragma unroll
+            for (int t = 0; t < NTC; ++t) acc32[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
     const int64_t rb = (int64_t)blockIdx.x * a.rows_per_blk;
     const int64_t re = min(a.n, rb + a.rows_per_blk);
     const int64_t step = 4LL * a.ks;
@@ -424,11 +520,11 @@ void gram_mfma_kernel(GramMArgs<T> a) {
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
                 const bool okp = (r + (int64_t)(j + p) * step) < re;
-                double xv[MTC], yv[NTC];
+                OpR xv[MTC], yv[NTC];
 #pragma unroll
                 for (int mt = 0; mt < MTC; ++mt) {
                     const int i = mt * 16 + li;
-                    xv[mt] = (okp && i < nbx) ? (double)xa[p][mt] : 0.0;
+                    xv[mt] = (okp && i < nbx) ? (OpR)xa[p][mt] : (OpR)0;
                 }
 #pragma unroll
                 for (int t = 0; t < NTC; ++t) {
@@ -441,30 +537,48 @@ void gram_mfma_kernel(GramMArgs<T> a) {
                         else
                             v = (jr & 1) ? yi : yr;
                     }
-                    yv[t] = v;
+                    yv[t] = (OpR)v;
                 }
 #pragma unroll
                 for (int mt = 0; mt < MTC; ++mt) {
                     if (mt < a.MT) {
 #pragma unroll
                         for (int t = 0; t < NTC; ++t)
-                            if (t < a.NTg && nt0 + t < a.NT)
-                                acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[mt], yv[t],
-                                                                                  acc[mt][t], 0, 0, 0);
+                            if (t < a.NTg && nt0 + t < a.NT) {
+                                if constexpr (F32)
+                                    acc32[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        xv[mt], yv[t], acc32[mt][t], 0, 0, 0);
+                                else
+                                    acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                        xv[mt], yv[t], acc[mt][t], 0, 0, 0);
+                            }
                     }
                 }
                 load(p, r + (int64_t)(j + p + PF) * step);
             }
+            if constexpr (F32) {
+                // end of a round: the FP32 tiles go into the FP64 accumulators
+#pragma unroll
+                for (int mt = 0; mt < MTC; ++mt)
+#pragma unroll
+                    for (int t = 0; t < NTC; ++t) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[mt][t][v] += (double)acc32[mt][t][v];
+                        acc32[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
         }
     }
-    // D(i, j) of a 16x16 tile (FP64 16x16x4 layout on gfx950): register v of
-    // lane l holds i = 4 v + l / 16, j = l % 16
+    // D(i, j) of a 16x16 tile on gfx950: register v of lane l holds j = l % 16
+    // and i = 4 v + l / 16 (FP64 16x16x4) or i = 4 (l / 16) + v (FP32 16x16x4)
     auto store = [&](int mt, int nt, const d4v &d) {
         const int jj = nt * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = mt * 16 + 4 * v + lk;
-            if (i < nbx && jj < nby) a.part[(int64_t)(i + jj * nbx) * a.nblk + blockIdx.x] = d[v];
+            const int i = mt * 16 + (F32 ? 4 * lk + v : 4 * v + lk);
+            // block-contiguous partials: this block's nbx-by-nby real Gram
+            if (i < nbx && jj < nby)
+                a.part[(int64_t)blockIdx.x * nbx * nby + i + (int64_t)jj * nbx] = d[v];
         }
     };
     if (a.ks == 1) {
@@ -509,29 +623,44 @@ void gram_mfma_kernel(GramMArgs<T> a) {
     }
 }
 
-// complex G(p, q) from the real partials: (rr + ii) + i (ri - ir)
+// complex G(p, q) = (rr + ii) + i (ri - ir) from the real partial Grams of
+// nblk blocks, stored block after block (part[blk E + i + j nbx], E = nbx nby,
+// nbx = 2 bx, nby = 2 by).  A workgroup takes 8 consecutive p of one column q:
+// the 32 reals of rows 2 p0 .. 2 p0 + 15 in real columns 2q and 2q + 1, i.e.
+// two contiguous 128-byte segments per block.  Thread t sums value t % 32 over
+// the blocks t / 32, t / 32 + 8, ... in that order, and the 8 partial sums
+// are added in LDS in a fixed order, so the result is reproducible bit for bit.
 __global__ __launch_bounds__(256) void reduce_real_partials_kernel(const double *part, int nblk,
-                                                                  int bx, double2 *out, int ldo) {
-    __shared__ double2 sh[256];
-    const int e = blockIdx.x;
-    const int p = e % bx, q = e / bx;
+                                                                  int bx, int by, double2 *out,
+                                                                  int ldo) {
+    __shared__ double sh[8][32];
     const int nbx = 2 * bx;
-    const double *rr = part + (int64_t)((2 * p) + (2 * q) * nbx) * nblk;
-    const double *ii = part + (int64_t)((2 * p + 1) + (2 * q + 1) * nbx) * nblk;
-    const double *ri = part + (int64_t)((2 * p) + (2 * q + 1) * nbx) * nblk;
-    const double *ir = part + (int64_t)((2 * p + 1) + (2 * q) * nbx) * nblk;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int i = threadIdx.x; i < nblk; i += 256) {
-        acc.x += rr[i] + ii[i];
-        acc.y += ri[i] - ir[i];
+    const int64_t E = (int64_t)nbx * 2 * by;
+    const int ptiles = (bx + 7) / 8;
+    const int p0 = (blockIdx.x % ptiles) * 8, q = blockIdx.x / ptiles;
+    const int t = threadIdx.x, v = t & 31, g = t >> 5;
+    const int i = 2 * p0 + (v & 15);   // real row
+    const int jc = 2 * q + (v >> 4);   // real column
+    double acc = 0.0;
+    if (i < nbx) {
+        const double *src = part + i + (int64_t)jc * nbx;
+        for (int blk = g; blk < nblk; blk += 8) acc += src[blk * E];
     }
-    sh[threadIdx.x] = acc;
+    sh[g][v] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = cadd(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
+    if (t < 32) {
+        double sum = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) sum += sh[gg][t];
+        sh[0][t] = sum;
     }
-    if (threadIdx.x == 0) out[p + (int64_t)q * ldo] = sh[0];
+    __syncthreads();
+    if (t < 8 && p0 + t < bx) {
+        // real column 2q: rows 2p (rr) and 2p + 1 (ir); column 2q + 1: ri, ii
+        const double rr = sh[0][2 * t], ir = sh[0][2 * t + 1];
+        const double ri = sh[0][16 + 2 * t], ii = sh[0][16 + 2 * t + 1];
+        out[p0 + t + (int64_t)q * ldo] = make_double2(rr + ii, ri - ir);
+    }
 }
 
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double2 *part, int nblk,
@@ -560,7 +689,7 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1, bool F32 = false>
 static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
                                 int ldo, int nblk_want) {
     a.G = (a.NT + NTC - 1) / NTC;
@@ -577,16 +706,17 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
     // no block starts past the last row
     a.nblk = (int)((a.n + a.rows_per_blk - 1) / a.rows_per_blk);
-    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC>), dim3(a.nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC, F32>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(a.bx * a.by), dim3(256), 0, st, a.part,
-                       a.nblk, a.bx, out, ldo);
+    hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(((a.bx + 7) / 8) * a.by), dim3(256), 0, st,
+                       a.part, a.nblk, a.bx, a.by, out, ldo);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T>
-void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
-                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo) {
+template <typename T, bool F32>
+static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
+                             int ldy, int by, const T *yscale, double2 *part, size_t part_cap,
+                             double2 *out, int ldo) {
     if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
     if (n <= 0) throw Error(-1, "gram: empty block");
     GramMArgs<T> a{};
@@ -611,39 +741,51 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
         // test basis): MT x 2 tiles per wave, rows split over the 4 waves; a
         // wider compiled tile set would only cost registers (4096000 rows:
         // 40 x 10 924 -> 633 us, 30 x 10 686 -> 526 us)
-        if (a.MT <= 2) gram_launch_variant<T, 2, 2>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 3) gram_launch_variant<T, 3, 2>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 4) gram_launch_variant<T, 4, 2>(st, a, part_cap, out, ldo, nb);
+        if (a.MT <= 2) gram_launch_variant<T, 2, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
         else if (a.MT == 5) {
-            if (tall) gram_launch_variant<T, 5, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 5, 2>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 5, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 5, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
         } else if (a.MT == 6) {
-            if (tall) gram_launch_variant<T, 6, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 6, 2>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 6, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 6, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
         } else {
-            if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 8, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 8, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
         }
     } else if (a.MT <= 3)
-        gram_launch_variant<T, 3, 3>(st, a, part_cap, out, ldo, nb);
+        gram_launch_variant<T, 3, 3, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4) {
-        if (tall) gram_launch_variant<T, 4, 4, 2, 2>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 4, 4>(st, a, part_cap, out, ldo, nb);
+        if (tall) gram_launch_variant<T, 4, 4, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 4, 4, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
     } else if (a.MT == 5)   // two K steps in flight: more would spill registers
-        gram_launch_variant<T, 5, 5, 2>(st, a, part_cap, out, ldo, nb);
+        gram_launch_variant<T, 5, 5, 2, 1, F32>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 6) {
-        if (tall) gram_launch_variant<T, 6, 3, 2, 2>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 6, 3>(st, a, part_cap, out, ldo, nb);
+        if (tall) gram_launch_variant<T, 6, 3, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 6, 3, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
     } else {
-        if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 8, 2>(st, a, part_cap, out, ldo, nb);
+        if (tall) gram_launch_variant<T, 8, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 8, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
     }
+}
+template <typename T>
+void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo,
+                 bool f32) {
+    if constexpr (sizeof(T) == 8) {
+        if (f32) {
+            launch_gram_impl<T, true>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
+            return;
+        }
+    }
+    launch_gram_impl<T, false>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
 }
 template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
                                    const double2 *, int, int, const double2 *, double2 *, size_t,
-                                   double2 *, int);
+                                   double2 *, int, bool);
 template void launch_gram<float2>(hipStream_t, int64_t, const float2 *, int, int, const float2 *,
-                                  int, int, const float2 *, double2 *, size_t, double2 *, int);
+                                  int, int, const float2 *, double2 *, size_t, double2 *, int, bool);
 
 // ---------------------------------------------------------------------------
 // row-local block update
@@ -791,7 +933,6 @@ __global__ __launch_bounds__(64) void update_kernel(UpdArgs<T> a) {
 // the next PF slabs (across terms and row groups) are in flight while a slab
 // is multiplied.  FP64 blocks use the FP64 MFMA; complex64 blocks the FP32
 // one (FP32 accumulation, as in the VALU kernel).
-typedef float f4v __attribute__((ext_vector_type(4)));
 template <typename T> struct UpdMma;
 template <> struct UpdMma<double2> {
     using R = double;
@@ -1080,7 +1221,8 @@ template void launch_update<float2>(hipStream_t, int64_t, float2 *, int, int, in
 // Cholesky-QR factor (one workgroup, w <= 64)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G, double2 *Rinv,
-                                                        int *status, double2 *Rout) {
+                                                        int *status, double2 *Rout, int wy,
+                                                        double2 *Cy, int guard) {
     // A holds the scaled Gram; its upper triangle becomes R (A = R^H R) and
     // its strict lower triangle then receives R^{-1} transposed (the diagonal
     // of R^{-1} goes to dinv).
@@ -1092,8 +1234,48 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     const int tid = threadIdx.x;
     const int lda = w + 1;
     if (tid == 0) flag = 0;
-    for (int e = tid; e < w * w; e += 256) A[e % w + (e / w) * lda] = G[e];
+    if (wy == 0) {
+        for (int e = tid; e < w * w; e += 256) A[e % w + (e / w) * lda] = G[e];
+    } else {
+        // G is [Y X]^H X ((wy + w)-by-w, leading dimension wy + w) for an
+        // orthonormal Y: rows 0..wy-1 hold G_Y = Y^H X, the rest X^H X.  The
+        // Gram of the projected block (X - Y G_Y) is X^H X - G_Y^H G_Y.
+        const int ldg = wy + w;
+        for (int e = tid; e < w * w; e += 256) {
+            const int i = e % w, j = e / w;
+            double2 v = G[wy + i + (size_t)j * ldg];
+            for (int t = 0; t < wy; ++t) {
+                const double2 a = G[t + (size_t)i * ldg], c = G[t + (size_t)j * ldg];
+                v.x -= a.x * c.x + a.y * c.y;   // conj(a) * c
+                v.y -= a.x * c.y - a.y * c.x;
+            }
+            A[i + j * lda] = v;
+        }
+    }
     __syncthreads();
+    if (wy > 0 && guard) {
+        // Cancellation guard: where the projected block keeps less than 1e-8
+        // of a column's (positive, finite) squared norm, X^H X - G_Y^H G_Y has
+        // lost more than half of its digits.  The pass then only projects
+        // (Rinv = I, Cy = -G_Y, i.e. X <- X - Y G_Y exactly as block
+        // Gram-Schmidt) and leaves the normalisation to the next pass.
+        if (tid < w) {
+            const double full = G[wy + tid + (size_t)tid * (wy + w)].x;
+            if (full > 0.0 && isfinite(full) && !(A[tid + tid * lda].x > 1e-8 * full)) flag = -1;
+        }
+        __syncthreads();
+        if (flag < 0) {
+            const int ldg = wy + w;
+            for (int e = tid; e < w * w; e += 256)
+                Rinv[e] = make_double2((e % w) == (e / w) ? 1.0 : 0.0, 0.0);
+            for (int e = tid; e < wy * w; e += 256) {
+                const int r = e % wy, j = e / wy;
+                const double2 g = G[r + (size_t)j * ldg];
+                Cy[e] = make_double2(-g.x, -g.y);
+            }
+            return;
+        }
+    }
     if (tid < w) {
         const double g = A[tid + tid * lda].x;
         const bool ok = (g > 0.0) && isfinite(g);
@@ -1197,6 +1379,24 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
             Rout[e] = r;
         }
     }
+    if (wy > 0) {
+        // Cy = -G_Y Rinv (wy-by-w, leading dimension wy): the coefficients of
+        // Y in (X - Y G_Y) Rinv; Rinv(i, j) = dsc[i] * (dinv[i] if i == j,
+        // A[j + i lda] if i < j)
+        const int ldg = wy + w;
+        for (int e = tid; e < wy * w; e += 256) {
+            const int r = e % wy, j = e / wy;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int i = 0; i <= j; ++i) {
+                const double2 ri = (i == j) ? make_double2(dinv[i] * dsc[i], 0.0)
+                                            : make_double2(A[j + i * lda].x * dsc[i], A[j + i * lda].y * dsc[i]);
+                const double2 g = G[r + (size_t)i * ldg];
+                acc.x += g.x * ri.x - g.y * ri.y;
+                acc.y += g.x * ri.y + g.y * ri.x;
+            }
+            Cy[e] = make_double2(-acc.x, -acc.y);
+        }
+    }
     __syncthreads();
     if (tid == 0 && flag > 0 && status) atomicAdd(status, flag);
 }
@@ -1204,13 +1404,65 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
 void launch_chol_rinv(hipStream_t st, int w, const double2 *G, double2 *Rinv, int *status,
                       double2 *Rout) {
     if (w < 1 || w > 48) throw Error(-1, "cholqr: width out of range");
-    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status, Rout);
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status, Rout, 0,
+                       (double2 *)nullptr, 0);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+void launch_chol_proj(hipStream_t st, int wy, int w, const double2 *G, double2 *Rinv, double2 *Cy,
+                      int *status, bool guard) {
+    if (w < 1 || w > 48 || wy < 0 || wy > 48 || wy + w > 64)
+        throw Error(-1, "cholqr: width out of range");
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256), 0, st, w, G, Rinv, status,
+                       (double2 *)nullptr, wy, Cy, guard ? 1 : 0);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
 // elementwise
 // ---------------------------------------------------------------------------
+// Y = X for row-major blocks moved as 16-byte vectors (one complex128 entry
+// or two complex64 entries): wv vectors per row, leading dimensions in
+// vectors.  Contiguous blocks stream with non-temporal loads and stores,
+// eight vectors in flight per thread, over a grid of 16384 workgroups (the
+// fastest of the configurations measured on a 524 MB block: 6.2 TB/s);
+// strided blocks copy one vector per thread and step.
+__global__ __launch_bounds__(256) void block_copy_kernel(int64_t n, int wv, const float4 *X,
+                                                         int64_t ldx, float4 *Y, int64_t ldy) {
+    typedef float f4n __attribute__((ext_vector_type(4)));
+    const int64_t total = n * wv;
+    const int64_t step = (int64_t)gridDim.x * 256;
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (ldx == wv && ldy == wv) {
+        const f4n *x = reinterpret_cast<const f4n *>(X);
+        f4n *y = reinterpret_cast<f4n *>(Y);
+        for (; e + 7 * step < total; e += 8 * step) {
+            f4n v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = __builtin_nontemporal_load(x + e + u * step);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) __builtin_nontemporal_store(v[u], y + e + u * step);
+        }
+        for (; e < total; e += step) y[e] = x[e];
+        return;
+    }
+    for (; e < total; e += step) {
+        const int64_t r = e / wv;
+        const int64_t c = e - r * wv;
+        Y[r * ldy + c] = X[r * ldx + c];
+    }
+}
+
+void launch_block_copy(hipStream_t st, int64_t n, int wv, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy) {
+    if (n <= 0 || wv <= 0) return;
+    const int64_t total = n * wv;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(block_copy_kernel, dim3(grid), dim3(256), 0, st, n, wv,
+                       static_cast<const float4 *>(X), ldx, static_cast<float4 *>(Y), ldy);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 __global__ void scale_rows_kernel(int64_t n, int w, const T *in, int ldi, const T *rs, T *out,
                                   int ldo) {

@@ -69,7 +69,8 @@ EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_
            "gplhr_get_eigvecs", "gplhr_get_eig", "gplhr_eig_backward", "gplhr_get_stats",
            "gplhr_destroy",
            "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram", "gplhr_jacobi",
-           "gplhr_block_update", "gplhr_gram_noalloc", "gplhr_get_residual_norms"]
+           "gplhr_block_update", "gplhr_gram_noalloc", "gplhr_get_residual_norms",
+           "gplhr_block_copy"]
 
 
 def lib():
@@ -114,6 +115,8 @@ def lib():
     L.gplhr_csr_plane.restype = i32
     L.gplhr_gram.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
     L.gplhr_gram.restype = i32
+    L.gplhr_block_copy.argtypes = [i32, i64, vp, i32, vp, i32, i32, vp]
+    L.gplhr_block_copy.restype = i32
     L.gplhr_gram_noalloc.argtypes = [i32, i64, vp, i32, i32, vp, i32, i32, vp, vp]
     L.gplhr_gram_noalloc.restype = i32
     L.gplhr_block_update.argtypes = [i32, i64, vp, i32, i32, vp, i32, vp, i32, i32,
@@ -361,6 +364,16 @@ def gram(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
     _check(lib().gplhr_gram(dtype, X.shape[0], _ptr(X), X.stride(0), bx, _ptr(Y), Y.stride(0),
                             by, _ptr(G), _stream_ptr()))
     return G.t()
+
+
+def block_copy(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+    """Y = X with the library's streaming block-copy kernel (row-major,
+    complex128 or complex64)."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[X.dtype]
+    assert X.dtype == Y.dtype and X.shape == Y.shape and X.stride(1) == 1 and Y.stride(1) == 1
+    _check(lib().gplhr_block_copy(dtype, X.shape[0], _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
+                                  X.shape[1], _stream_ptr()))
+    return Y
 
 
 def gram_noalloc(X: torch.Tensor, Y: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
