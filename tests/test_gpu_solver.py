@@ -269,7 +269,9 @@ def _d1_reference():
                                          ("fp64", dict(locking=True)),
                                          ("mixed", dict(locking=True)),
                                          ("fp64", dict(algorithm="eig")),
-                                         ("mixed", dict(algorithm="eig"))])
+                                         ("mixed", dict(algorithm="eig")),
+                                         ("fp64", dict(p_mode="lobpcg")),
+                                         ("fp64", dict(p_mode="none"))])
 def test_converged_parity_full_size(device, precision, kw):
     # n = 262144, k = 10, B = diag U[1,2], diagonal preconditioner; the
     # eigenvalues are those of the FP64 oracle (Schur form) whatever the form
@@ -687,3 +689,106 @@ def test_trajectory_parity_full_size_160cube(device, precision):
 @functools.lru_cache(maxsize=None)
 def _c5_oracle_trajectory(its):
     return tuple(O.solve_problem(problems.config("c5"), tol=0.0, maxit=its).lam_history)
+
+
+def test_backward_matches_dense_derivatives_random_pencil(device):
+    # the random-pencil generator of the gradient workload at n = 2048
+    # (16 random off-diagonal entries per row plus the shifted diagonal;
+    # B = I + 0.1 S), sigma = 0, k = 8: the 8th and 9th eigenvalues nearest
+    # sigma are 2e-4 apart in distance, so the solve uses the stronger T of
+    # Section 4 (6 block GMRES steps over the diagonal) and a 10-column block.
+    # Loss sum |lambda_i - sigma|^2; gradients on every stored entry of A and
+    # B against the FP64 eigenvalue derivatives from left and right
+    # eigenvectors computed independently of GPLHR
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    p = problems.config("c4", 2048)
+    n, k, sigma = p.n, p.k, p.sigma
+    dA, dB = G.DeviceCsr.from_host(p.A), G.DeviceCsr.from_host(p.B)
+    valA = dA.val.clone().requires_grad_(True)
+    valB = dB.val.clone().requires_grad_(True)
+    lam = G.GPLHREig.apply(valA, valB, dA, dB, sigma, k,
+                           dict(precond="gmres", steps=6, inner="diag", block=10, tol=1e-12,
+                                max_iter=3000,
+                                V0=torch.as_tensor(problems.start_block(n, 10)).to("cuda")))
+    loss = torch.sum(torch.abs(lam - sigma) ** 2)
+    loss.backward()
+    gA, gB = valA.grad.cpu().numpy(), valB.grad.cpu().numpy()
+    As, Bs = p.A.to_scipy(), p.B.to_scipy()
+    ra = np.repeat(np.arange(n), np.diff(p.A.indptr))
+    rb = np.repeat(np.arange(n), np.diff(p.B.indptr))
+    # reference eigentriplets by ARPACK shift-and-invert (pinned against
+    # LAPACK's dense zggev in tests/test_oracle_gradient.py; the dense solve
+    # with both eigenvector sets takes minutes at n = 2048)
+    lam_ref, _, _ = OG.nearest_eigs_sparse(As, Bs, sigma, k)
+    lam_g = lam.detach().cpu().numpy()
+    assert match_err(lam_g, lam_ref) < 1e-10
+    order = [int(np.argmin(np.abs(lam_ref - l))) for l in lam_g]
+    assert sorted(order) == list(range(k))
+    g_ref = np.zeros(k, dtype=complex)
+    g_ref[order] = 2 * (lam_g - sigma)
+    _, gA_ref, gB_ref = OG.eig_grad(As, Bs, sigma, k, g_ref, ra, p.A.indices, rb, p.B.indices,
+                                    sparse=True)
+    errA = np.max(np.abs(gA - gA_ref)) / np.max(np.abs(gA_ref))
+    errB = np.max(np.abs(gB - gB_ref)) / np.max(np.abs(gB_ref))
+    print(f"c4 n=2048 gradient vs dense derivatives: A {errA:.2e}, B {errB:.2e}", flush=True)
+    assert errA <= 1e-8 and errB <= 1e-8
+
+
+def test_backward_matches_central_differences_random_pencil(device):
+    # the same workload: the GPU gradient of sum |lambda_i - sigma|^2 against
+    # central differences (step 1e-6, real and imaginary directions) on 8
+    # seeded stored entries (6 of A, 2 of B).  Each perturbed solve starts
+    # from the unperturbed Schur vectors (plus two seeded columns) and goes
+    # to 1e-13, near the FP64 floor, so that the differences resolve the
+    # derivatives (about 1e-2) to better than 1e-4 relative.
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    p = problems.config("c4", 2048)
+    n, k, sigma = p.n, p.k, p.sigma
+    dA, dB = G.DeviceCsr.from_host(p.A), G.DeviceCsr.from_host(p.B)
+    opts = dict(precond="gmres", steps=6, inner="diag", block=10, tol=1e-13, max_iter=3000)
+    valA = dA.val.clone().requires_grad_(True)
+    valB = dB.val.clone().requires_grad_(True)
+    V0 = torch.as_tensor(problems.start_block(n, 10)).to("cuda")
+    lam = G.GPLHREig.apply(valA, valB, dA, dB, sigma, k, dict(opts, V0=V0))
+    torch.sum(torch.abs(lam - sigma) ** 2).backward()
+    gA, gB = valA.grad.cpu().numpy(), valB.grad.cpu().numpy()
+    # the unperturbed Schur vectors as the warm start of every perturbed solve
+    s0 = G.Solver(dA, dB, sigma, k, precond="gmres", steps=6, inner="diag", block=10,
+                  tol=1e-13, max_iter=3000, V0=V0)
+    assert s0.iterate()[0] == 0
+    V = s0.schur()["V"]
+    s0.close()
+    extra = torch.as_tensor(problems.start_block(n, 2, seed=5)).to("cuda")
+    Vw = torch.cat([V, extra], dim=1).contiguous()
+
+    def loss_at(valA_, valB_):
+        A2 = G.DeviceCsr(dA.n, dA.row_ptr, dA.col_idx, valA_)
+        B2 = G.DeviceCsr(dB.n, dB.row_ptr, dB.col_idx, valB_)
+        s = G.Solver(A2, B2, sigma, k, precond="gmres", steps=6, inner="diag", block=10,
+                     tol=1e-13, max_iter=3000, V0=Vw)
+        st, _, res = s.iterate()
+        lam_ = s.lam()
+        s.close()
+        assert st == 0, res
+        return float(np.sum(np.abs(lam_[:k] - sigma) ** 2))
+
+    rng = np.random.default_rng(44)
+    h = 1e-6
+    gmax = max(np.abs(gA).max(), np.abs(gB).max())
+    for which, val, g, count in (("A", dA.val, gA, 6), ("B", dB.val, gB, 2)):
+        for e in rng.choice(val.numel(), size=count, replace=False):
+            fd = 0j
+            for unit in (1.0, 1j):
+                vp, vm = val.clone(), val.clone()
+                vp[int(e)] += h * unit
+                vm[int(e)] -= h * unit
+                if which == "A":
+                    lp, lm = loss_at(vp, dB.val), loss_at(vm, dB.val)
+                else:
+                    lp, lm = loss_at(dA.val, vp), loss_at(dA.val, vm)
+                fd += unit * (lp - lm) / (2 * h)
+            print(f"c4 n=2048 entry {which}[{e}]: gradient {g[e]:.6e}, central difference {fd:.6e}",
+                  flush=True)
+            assert abs(g[e] - fd) <= 1e-4 * gmax, (which, e, g[e], fd)

@@ -60,3 +60,30 @@ def test_matches_central_differences(seed):
                     lm, _ = loss_and_lam(A, Mm, sigma, k)
                 fd += unit * (lp - lm) / (2 * h)
             assert abs(G[t] - fd) <= 1e-6 * max(1.0, abs(fd)), (which, i, j, G[t], fd)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_sparse_reference_matches_dense(seed):
+    # the ARPACK shift-and-invert triplets give the same eigenvalues and the
+    # same gradients as LAPACK on the dense pencil (random sparse pencil of
+    # the gradient workload's family, n = 400)
+    import scipy.sparse as sp
+    from paper_1506_06829_amd import problems
+    Acsr, Bcsr = problems.random_pencil(400, seed=seed)
+    A, B = Acsr.to_scipy(), Bcsr.to_scipy()
+    sigma, k = 0.0 + 0.0j, 6
+    lam_d, _, _ = OG.nearest_eigs_dense(A.toarray(), B.toarray(), sigma, k)
+    lam_s, Y, X = OG.nearest_eigs_sparse(A, B, sigma, k)
+    np.testing.assert_allclose(lam_s, lam_d, rtol=1e-11)
+    # left and right eigenvectors satisfy their equations
+    for e in range(k):
+        np.testing.assert_allclose(A @ X[:, e], lam_s[e] * (B @ X[:, e]), atol=1e-10 * np.abs(lam_s[e]))
+        np.testing.assert_allclose(Y[:, e].conj() @ A, lam_s[e] * (Y[:, e].conj() @ B),
+                                   atol=1e-10 * np.abs(lam_s[e]))
+    g = 2 * (lam_d - sigma)
+    ra = np.repeat(np.arange(400), np.diff(A.indptr))
+    rb = np.repeat(np.arange(400), np.diff(B.indptr))
+    _, gA_d, gB_d = OG.eig_grad_dense(A.toarray(), B.toarray(), sigma, k, g, ra, A.indices, rb, B.indices)
+    _, gA_s, gB_s = OG.eig_grad(A, B, sigma, k, g, ra, A.indices, rb, B.indices, sparse=True)
+    assert np.max(np.abs(gA_s - gA_d)) <= 1e-10 * np.max(np.abs(gA_d))
+    assert np.max(np.abs(gB_s - gB_d)) <= 1e-10 * np.max(np.abs(gB_d))
