@@ -367,10 +367,8 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     // F2 follows F1 in one buffer, so both come back in one copy
     const size_t ss = (size_t)s_cur * s_cur;
     double2 *F2 = F1 + ss;
-    // (in the complex64 phase on the FP32 MFMA with FP64 accumulation across
-    // rows, the precision of its operands; Section 3.3's pencil)
-    gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1, true);
-    gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2, true);
+    gram<T>(w.U, ld, s_cur, w.CZ, ld, s_cur, nullptr, F1);
+    gram<T>(w.U, ld, s_cur, bsrc, ld, s_cur, bsc, F2);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, fbase, (1 + 2 * ss) * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     tflush();

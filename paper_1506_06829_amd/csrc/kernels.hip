@@ -960,18 +960,15 @@ struct UpdCursor {
     int t, s;    // term, slab of 8 input columns within the term
 };
 
-template <typename T, int MT, int NT, int PF>
-__global__ __launch_bounds__(256) void update_mfma_kernel(UpdArgs<T> a, int kpad) {
-    using R = typename UpdMma<T>::R;
-    using V = typename UpdMma<T>::V;
-    constexpr int WOP = 8 * NT;   // complex output columns covered by the tiles
-    extern __shared__ double2 sh_mfma_raw[];
-    T *sM = reinterpret_cast<T *>(sh_mfma_raw);   // kpad x WOP, row-major
+// The coefficients alpha_t M_t of all terms as one kpad x wop complex block
+// in LDS (row-major; each term's rows padded to a multiple of 8, columns past
+// wout zero), followed by a barrier.
+template <typename T>
+__device__ __forceinline__ void stage_update_coeffs(const UpdArgs<T> &a, int kpad, int wop, T *sM) {
     const int nterms = a.nterms;
-    const int w0 = a.t[0].w, w1 = nterms > 1 ? a.t[1].w : 0, w2 = nterms > 2 ? a.t[2].w : 0;
-    const int p0 = pad8(w0), p1 = pad8(w1);
-    for (int e = threadIdx.x; e < kpad * WOP; e += 256) {
-        const int j = e / WOP, c = e - j * WOP;
+    const int p0 = pad8(a.t[0].w), p1 = nterms > 1 ? pad8(a.t[1].w) : 0;
+    for (int e = threadIdx.x; e < kpad * wop; e += blockDim.x) {
+        const int j = e / wop, c = e - j * wop;
         int t = 0, jj = j;
         if (jj >= p0) {
             jj -= p0;
@@ -986,6 +983,19 @@ __global__ __launch_bounds__(256) void update_mfma_kernel(UpdArgs<T> a, int kpad
         sM[e] = v;
     }
     __syncthreads();
+}
+
+template <typename T, int MT, int NT, int PF>
+__global__ __launch_bounds__(256) void update_mfma_kernel(UpdArgs<T> a, int kpad) {
+    using R = typename UpdMma<T>::R;
+    using V = typename UpdMma<T>::V;
+    constexpr int WOP = 8 * NT;   // complex output columns covered by the tiles
+    extern __shared__ double2 sh_mfma_raw[];
+    T *sM = reinterpret_cast<T *>(sh_mfma_raw);   // kpad x WOP, row-major
+    const int nterms = a.nterms;
+    const int w0 = a.t[0].w, w1 = nterms > 1 ? a.t[1].w : 0, w2 = nterms > 2 ? a.t[2].w : 0;
+    const int p0 = pad8(w0), p1 = pad8(w1);
+    stage_update_coeffs(a, kpad, WOP, sM);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const bool odd = li & 1;
@@ -1124,6 +1134,280 @@ static void launch_update_mfma(hipStream_t st, const UpdArgs<T> &a, int kpad) {
     hipLaunchKernelGGL((update_mfma_kernel<T, MT, NT, 2>), dim3(grid), dim3(256), shmem, st, a, kpad);
 }
 
+// Pipelined MFMA kernel for the streaming shapes (inputs at most 64 complex
+// columns, no row scaling).  A wavefront owns row groups of 16 MT rows, as in
+// update_mfma_kernel, but loads all S slabs of its next row group, and that
+// group's Out rows when beta != 0, into a second register buffer while it
+// multiplies the current one, so a whole row group's reads are in flight
+// behind every multiply.  The product tile then passes through a
+// wave-private LDS tile and leaves as coalesced 16-byte chunks of Out rows
+// (one complex128 or two complex64 per lane), read-modify-write included.
+// Complex64 blocks need even widths, leading dimensions and column offsets
+// (16-byte input pairs and output chunks); the launcher checks that.
+template <typename T> struct UpdChunk;
+template <> struct UpdChunk<float2> { using C = float4; static constexpr int CPC = 2; };
+template <> struct UpdChunk<double2> { using C = double2; static constexpr int CPC = 1; };
+
+// LDS written by some lanes of a wavefront and then read by others: the
+// wavefront's LDS operations complete in order, and the fences keep the
+// compiler from moving them across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int MT, int NT>
+struct UpdPipeShape {
+    using R = typename UpdMma<T>::R;
+    static constexpr int WOP = 8 * NT;                         // complex output columns
+    static constexpr int ROWS = 16 * MT;                       // rows per row group
+    static constexpr int LDR = 2 * WOP + 16 / (int)sizeof(R);  // reals per LDS tile row
+    static constexpr int CPC = UpdChunk<T>::CPC;
+    static constexpr int CPR = WOP / CPC;                      // chunks per row
+    static constexpr int NCH = ROWS * CPR / 64;                // chunks per lane
+    static_assert((ROWS * CPR) % 64 == 0, "whole chunks per lane");
+    static size_t shmem(int kpad) {
+        return sizeof(T) * (size_t)kpad * WOP + (size_t)4 * ROWS * LDR * sizeof(R);
+    }
+};
+
+template <typename T, int MT, int NT, int SMAX>
+__global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad, int nslab, int nts) {
+    using Sh = UpdPipeShape<T, MT, NT>;
+    using R = typename UpdMma<T>::R;
+    using V = typename UpdMma<T>::V;
+    using C = typename UpdChunk<T>::C;
+    constexpr int WOP = Sh::WOP, ROWS = Sh::ROWS, LDR = Sh::LDR, CPC = Sh::CPC, CPR = Sh::CPR,
+                  NCH = Sh::NCH;
+    extern __shared__ double2 sh_mfma_raw[];
+    T *sM = reinterpret_cast<T *>(sh_mfma_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    R *sO = reinterpret_cast<R *>(sM + (size_t)kpad * WOP) + (size_t)wave * ROWS * LDR;
+    stage_update_coeffs(a, kpad, WOP, sM);
+    const int li = lane & 15, lk = lane >> 4;
+    const bool odd = li & 1;
+    // slab i of a row group: term st_t[i], its slab st_s[i], LDS row st_k[i]
+    int st_t[SMAX], st_s[SMAX], st_k[SMAX];
+    {
+        int t = 0, s = 0, k = 0;
+#pragma unroll
+        for (int i = 0; i < SMAX; ++i) {
+            while (t + 1 < a.nterms && s * 8 >= a.t[t].w) { s = 0; ++t; }
+            st_t[i] = t;
+            st_s[i] = s;
+            st_k[i] = k;
+            ++s;
+            k += 8;
+        }
+    }
+    const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
+    const T beta = from_d<T>(a.beta);
+    T bx[2][SMAX][MT][2];
+    C bd[2][NCH];
+    auto load = [&](int p, int64_t g) {
+#pragma unroll
+        for (int i = 0; i < SMAX; ++i) {
+            if (i < nslab) {
+                const UpdTerm<T> &tm = a.t[st_t[i]];
+                const int col0 = st_s[i] * 8 + 2 * lk;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    int64_t row = g + mt * 16 + li;
+                    row = row < a.n ? row : a.n - 1;
+                    const T *rp = tm.in + row * tm.ld + tm.col;
+                    if constexpr (sizeof(T) == 8) {
+                        // even width: entries col0 and col0 + 1 exist together
+                        const float4 v = *reinterpret_cast<const float4 *>(rp + (col0 < tm.w ? col0 : 0));
+                        bx[p][i][mt][0] = make_float2(v.x, v.y);
+                        bx[p][i][mt][1] = make_float2(v.z, v.w);
+                    } else {
+                        bx[p][i][mt][0] = rp[col0 < tm.w ? col0 : 0];
+                        bx[p][i][mt][1] = rp[col0 + 1 < tm.w ? col0 + 1 : 0];
+                    }
+                }
+            }
+        }
+        if (use_beta) {
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                const int e = q * 64 + lane;
+                const int rr = e / CPR, c0 = (e - rr * CPR) * CPC;
+                int64_t row = g + rr;
+                row = row < a.n ? row : a.n - 1;
+                const int c = c0 < a.wout ? c0 : 0;
+                const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+                bd[p][q] = *reinterpret_cast<const C *>(a.out + row * a.ldo + oc);
+            }
+        }
+    };
+    auto compute_store = [&](int p, int64_t g) {
+        V acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < SMAX; ++i) {
+            if (i < nslab) {
+                const UpdTerm<T> &tm = a.t[st_t[i]];
+                const int col0 = st_s[i] * 8 + 2 * lk;
+                const T *mrow = sM + (int64_t)(st_k[i] + 2 * lk) * WOP + (li >> 1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    T m[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) m[nt] = mrow[h * WOP + nt * 8];
+                    const bool ok = col0 + h < tm.w;
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        R bv[NT];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            bv[nt] = part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const T x = bx[p][i][mt][h];
+                            const R av = ok ? (part == 0 ? x.x : x.y) : (R)0;
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt)
+                                acc[mt][nt] = UpdMma<T>::mma(av, bv[nt], acc[mt][nt]);
+                        }
+                    }
+                }
+            }
+        }
+        // tile -> LDS: register v of lane (li, lk) is real column nt * 16 + li
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    sO[(mt * 16 + UpdMma<T>::row(v, lk)) * LDR + nt * 16 + li] = acc[mt][nt][v];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            const int e = q * 64 + lane;
+            const int rr = e / CPR, c = (e - rr * CPR) * CPC;
+            const int64_t row = g + rr;
+            C o = *reinterpret_cast<const C *>(sO + rr * LDR + 2 * c);
+            if (row < a.n && c < a.wout) {
+                const int oc = (c < a.split) ? (a.ocol + c) : (a.ocol2 + c - a.split);
+                if (a.add) {
+                    const C ad = *reinterpret_cast<const C *>(a.add + row * a.ldadd + c);
+                    o.x += ad.x;
+                    o.y += ad.y;
+                    if constexpr (CPC == 2) { o.z += ad.z; o.w += ad.w; }
+                }
+                if (use_beta) {
+                    const C d = bd[p][q];
+                    o.x += beta.x * d.x - beta.y * d.y;
+                    o.y += beta.x * d.y + beta.y * d.x;
+                    if constexpr (CPC == 2) {
+                        o.z += beta.x * d.z - beta.y * d.w;
+                        o.w += beta.x * d.w + beta.y * d.z;
+                    }
+                }
+                C *dst = reinterpret_cast<C *>(a.out + row * a.ldo + oc);
+                if (nts) {
+                    if constexpr (CPC == 2) {
+                        typedef float f4n __attribute__((ext_vector_type(4)));
+                        __builtin_nontemporal_store(f4n{o.x, o.y, o.z, o.w}, reinterpret_cast<f4n *>(dst));
+                    } else {
+                        typedef double d2n __attribute__((ext_vector_type(2)));
+                        __builtin_nontemporal_store(d2n{o.x, o.y}, reinterpret_cast<d2n *>(dst));
+                    }
+                } else {
+                    *dst = o;
+                }
+            }
+        }
+        // the next tile may overwrite sO only after every lane has read it
+        wave_lds_sync();
+    };
+    // row groups g0, g0 + stride, ...: buffer 0 holds the even ones, buffer 1
+    // the odd ones (static register indices)
+    const int64_t stride = (int64_t)gridDim.x * 4 * ROWS;
+    int64_t g = ((int64_t)blockIdx.x * 4 + wave) * ROWS;
+    if (g < a.n) load(0, g);
+    while (g < a.n) {
+        const int64_t g1 = g + stride;
+        if (g1 < a.n) load(1, g1);
+        compute_store(0, g);
+        g = g1;
+        if (g >= a.n) break;
+        const int64_t g2 = g + stride;
+        if (g2 < a.n) load(0, g2);
+        compute_store(1, g);
+        g = g2;
+    }
+}
+
+template <typename T, int MT, int NT, int SMAX>
+static void launch_update_pipe(hipStream_t st, const UpdArgs<T> &a, int kpad) {
+    constexpr int64_t rows = 16 * MT;
+    const int64_t waves = (a.n + rows - 1) / rows;
+    // workgroups in flight, by measurement at 4096000 rows: 4096 for up to 4
+    // slabs per row group (16 -> 16 complex64 with beta = 1: 417 -> 299 us
+    // against update_mfma_kernel), fewer for the wider ones whose register
+    // buffers are larger
+    const int cap = SMAX <= 4 ? 4096 : (sizeof(T) == 8 ? 1024 : 2048);
+    const int grid = (int)std::min<int64_t>((waves + 3) / 4, cap);
+    // outputs larger than the last-level caches stream past them
+    const int nts = (double)a.n * a.wout * sizeof(T) > 256.0 * 1024 * 1024;
+    const size_t shmem = UpdPipeShape<T, MT, NT>::shmem(kpad);
+    hipLaunchKernelGGL((update_pipe_kernel<T, MT, NT, SMAX>), dim3(grid), dim3(256), shmem, st, a,
+                       kpad, kpad / 8, nts);
+}
+
+// The pipelined kernel when the shape allows it (see update_pipe_kernel).
+template <typename T, int MT, int NT>
+static bool update_pipe_shape(hipStream_t st, const UpdArgs<T> &a, int kpad) {
+    if (UpdPipeShape<T, MT, NT>::shmem(kpad) > 64 * 1024) return false;
+    const int ns = kpad / 8;
+    if (ns <= 2) launch_update_pipe<T, MT, NT, 2>(st, a, kpad);
+    else if (ns <= 4) launch_update_pipe<T, MT, NT, 4>(st, a, kpad);
+    else if (ns <= 8) launch_update_pipe<T, MT, NT, 8>(st, a, kpad);
+    else return false;
+    return true;
+}
+
+template <typename T>
+static bool update_pipe(const UpdArgs<T> &a, int kpad, hipStream_t st) {
+    if (a.nterms < 1 || kpad < 8 || kpad > 64) return false;
+    auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (!al16(a.out) || (a.add && !al16(a.add))) return false;
+    for (int t = 0; t < a.nterms; ++t) {
+        const UpdTerm<T> &tm = a.t[t];
+        if (tm.rowscale || !al16(tm.in)) return false;
+        if (sizeof(T) == 8 && ((tm.ld | tm.col | tm.w) & 1)) return false;
+    }
+    if (sizeof(T) == 8) {
+        if ((a.wout | a.ocol | a.ocol2 | a.ldo) & 1) return false;
+        if (a.split < a.wout && (a.split & 1)) return false;
+        if (a.add && (a.ldadd & 1)) return false;
+    }
+    const int nt = (a.wout + 7) / 8;
+    if constexpr (sizeof(T) == 8) {
+        switch (nt) {
+            case 1: return update_pipe_shape<T, 2, 1>(st, a, kpad);
+            case 2: return update_pipe_shape<T, 2, 2>(st, a, kpad);
+            case 3: return update_pipe_shape<T, 1, 3>(st, a, kpad);
+            case 4: return update_pipe_shape<T, 1, 4>(st, a, kpad);
+            default: return false;
+        }
+    } else {
+        switch (nt) {
+            case 1: return update_pipe_shape<T, 1, 1>(st, a, kpad);
+            case 2: return update_pipe_shape<T, 1, 2>(st, a, kpad);
+            case 3: return update_pipe_shape<T, 1, 3>(st, a, kpad);
+            case 4: return update_pipe_shape<T, 1, 4>(st, a, kpad);
+            default: return false;
+        }
+    }
+}
+
 // MFMA or VALU kernel, by measurement on the solver's shapes (4096000 and
 // 262144 rows): in FP64 the MFMA kernel is as fast or faster for every shape;
 // for complex64 it wins once the output is wider than 16 columns, Out is
@@ -1188,7 +1472,7 @@ void launch_update(hipStream_t st, int64_t n, T *out, int ldo, int wout, int oco
     a.wtot = wtot;
     int kpad = 0;
     for (int t = 0; t < nterms; ++t) kpad += pad8(terms[t].w);
-    if (update_mfma<T>(a, kpad, st)) {
+    if (update_pipe<T>(a, kpad, st) || update_mfma<T>(a, kpad, st)) {
         GPLHR_HIP_CHECK(hipGetLastError());
         return;
     }
