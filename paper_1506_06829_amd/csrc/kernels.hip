@@ -10,6 +10,8 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
+#include <mutex>
+#include <set>
 #include <cstdint>
 #include <type_traits>
 #include <vector>
@@ -1372,6 +1374,25 @@ static void launch_update_mfma(hipStream_t st, const UpdArgs<T> &a, int kpad) {
     hipLaunchKernelGGL((update_mfma_kernel<T, MT, NT, 2>), dim3(grid), dim3(256), shmem, st, a, kpad);
 }
 
+// Launch with dynamic LDS, raising the kernel's limit above the 64 KiB
+// default when it needs more (gfx950: 160 KiB per workgroup), once per
+// kernel and device.
+static void allow_large_lds(const void *kernel) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = 0;
+    GPLHR_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({dev, kernel})) return;
+    GPLHR_HIP_CHECK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    done.insert({dev, kernel});
+}
+template <typename K, typename... Args>
+static void launch_lds_kernel(K kernel, int grid, size_t shmem, hipStream_t st, Args... args) {
+    if (shmem > 64 * 1024) allow_large_lds(reinterpret_cast<const void *>(kernel));
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), shmem, st, args...);
+}
+
 // Pipelined MFMA kernel for the streaming shapes (inputs at most 64 complex
 // columns, no row scaling).  A wavefront owns row groups of 16 MT rows, as in
 // update_mfma_kernel, but loads all S slabs of its next row group, and that
@@ -1410,7 +1431,8 @@ struct UpdPipeShape {
     }
 };
 
-template <typename T, int MT, int NT, int SMAX>
+// BETA: Out is read (beta != 0); without it no Out buffer is held.
+template <typename T, int MT, int NT, int SMAX, bool BETA>
 __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad, int nslab, int nts) {
     using Sh = UpdPipeShape<T, MT, NT>;
     using R = typename UpdMma<T>::R;
@@ -1439,10 +1461,9 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
             k += 8;
         }
     }
-    const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
     const T beta = from_d<T>(a.beta);
     T bx[2][SMAX][MT][2];
-    C bd[2][NCH];
+    C bd[2][BETA ? NCH : 1];
     auto load = [&](int p, int64_t g) {
 #pragma unroll
         for (int i = 0; i < SMAX; ++i) {
@@ -1466,7 +1487,7 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
                 }
             }
         }
-        if (use_beta) {
+        if constexpr (BETA) {
 #pragma unroll
             for (int q = 0; q < NCH; ++q) {
                 const int e = q * 64 + lane;
@@ -1538,7 +1559,7 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
                     o.y += ad.y;
                     if constexpr (CPC == 2) { o.z += ad.z; o.w += ad.w; }
                 }
-                if (use_beta) {
+                if constexpr (BETA) {
                     const C d = bd[p][q];
                     o.x += beta.x * d.x - beta.y * d.y;
                     o.y += beta.x * d.y + beta.y * d.x;
@@ -1584,6 +1605,7 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
 
 template <typename T, int MT, int NT, int SMAX>
 static void launch_update_pipe(hipStream_t st, const UpdArgs<T> &a, int kpad) {
+    const bool beta = (a.beta.x != 0.0 || a.beta.y != 0.0);
     constexpr int64_t rows = 16 * MT;
     const int64_t waves = (a.n + rows - 1) / rows;
     // workgroups in flight, by measurement at 4096000 rows: 4096 for up to 4
@@ -1595,14 +1617,16 @@ static void launch_update_pipe(hipStream_t st, const UpdArgs<T> &a, int kpad) {
     // outputs larger than the last-level caches stream past them
     const int nts = (double)a.n * a.wout * sizeof(T) > 256.0 * 1024 * 1024;
     const size_t shmem = UpdPipeShape<T, MT, NT>::shmem(kpad);
-    hipLaunchKernelGGL((update_pipe_kernel<T, MT, NT, SMAX>), dim3(grid), dim3(256), shmem, st, a,
-                       kpad, kpad / 8, nts);
+    if (beta)
+        launch_lds_kernel(update_pipe_kernel<T, MT, NT, SMAX, true>, grid, shmem, st, a, kpad, kpad / 8, nts);
+    else
+        launch_lds_kernel(update_pipe_kernel<T, MT, NT, SMAX, false>, grid, shmem, st, a, kpad, kpad / 8, nts);
 }
 
 // The pipelined kernel when the shape allows it (see update_pipe_kernel).
 template <typename T, int MT, int NT>
 static bool update_pipe_shape(hipStream_t st, const UpdArgs<T> &a, int kpad) {
-    if (UpdPipeShape<T, MT, NT>::shmem(kpad) > 64 * 1024) return false;
+    if (UpdPipeShape<T, MT, NT>::shmem(kpad) > 160 * 1024) return false;
     const int ns = kpad / 8;
     if (ns <= 2) launch_update_pipe<T, MT, NT, 2>(st, a, kpad);
     else if (ns <= 4) launch_update_pipe<T, MT, NT, 4>(st, a, kpad);
@@ -1633,6 +1657,8 @@ static bool update_pipe(const UpdArgs<T> &a, int kpad, hipStream_t st) {
             case 2: return update_pipe_shape<T, 2, 2>(st, a, kpad);
             case 3: return update_pipe_shape<T, 1, 3>(st, a, kpad);
             case 4: return update_pipe_shape<T, 1, 4>(st, a, kpad);
+            case 5: return update_pipe_shape<T, 1, 5>(st, a, kpad);
+            case 6: return update_pipe_shape<T, 1, 6>(st, a, kpad);
             default: return false;
         }
     } else {
@@ -1641,6 +1667,8 @@ static bool update_pipe(const UpdArgs<T> &a, int kpad, hipStream_t st) {
             case 2: return update_pipe_shape<T, 1, 2>(st, a, kpad);
             case 3: return update_pipe_shape<T, 1, 3>(st, a, kpad);
             case 4: return update_pipe_shape<T, 1, 4>(st, a, kpad);
+            case 5: return update_pipe_shape<T, 1, 5>(st, a, kpad);
+            case 6: return update_pipe_shape<T, 1, 6>(st, a, kpad);
             default: return false;
         }
     }
