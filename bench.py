@@ -35,16 +35,16 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # The kernel behind the largest share of a 160^3 mixed iteration: the
-# complex64 16 -> 16 row-local update with beta = 1 (X <- X - Y G of the
-# projections), timed on its own at the solver's shape.
-DOMINANT_KERNEL_PROBE = "block update c64 16->16 (beta=1)"
+# LDS-staged Gram of the projected pencil, complex64 64 x 64 over 4096000 rows
+# on the FP64 MFMA, timed on its own at the solver's shape.
+DOMINANT_KERNEL_PROBE = "Gram c64 64x64"
 # HBM-side bytes per launch of that probe from rocprofv3 (FETCH_SIZE scaled
 # by 2.000 and WRITE_SIZE by 1.000, the factors being what the same counters
 # read for a 256 MiB device copy), valid only for the kernels.hip whose
 # SHA-256 prefix is recorded with it; any later change to that file makes the
 # reported traffic null until the counters are taken again.
-DOMINANT_KERNEL_TRAFFIC = None       # bytes per launch
-DOMINANT_KERNEL_TRAFFIC_SRC = None   # sha256 prefix of kernels.hip
+DOMINANT_KERNEL_TRAFFIC = 4261224480          # bytes per launch
+DOMINANT_KERNEL_TRAFFIC_SRC = "6b2708595ffbf7f8"   # sha256 prefix of kernels.hip
 
 
 def kernels_source_sha():
@@ -182,7 +182,7 @@ def kernel_rooflines(G, torch):
             rf = {"bound": "mfma", "achieved": flops / ms / 1e9, "peak": peak_tf, "unit": "TFLOP/s"}
         rf["frac"] = rf["achieved"] / rf["peak"]
         name = f"block update {dt} {wx}->{wy}" + (" (beta=1)" if beta else "")
-        if name == DOMINANT_KERNEL_PROBE and DOMINANT_KERNEL_TRAFFIC_SRC == kernels_source_sha():
+        if name.startswith(DOMINANT_KERNEL_PROBE) and DOMINANT_KERNEL_TRAFFIC_SRC == kernels_source_sha():
             rf["traffic"] = DOMINANT_KERNEL_TRAFFIC
         out.append(dict(kernel=name, n=n, ms=ms, bytes=nbytes, flops=flops, **rf))
         del X, Y, M
@@ -203,8 +203,10 @@ def kernel_rooflines(G, torch):
         else:
             rf = {"bound": "mfma", "achieved": flops / ms / 1e9, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
         rf["frac"] = rf["achieved"] / rf["peak"]
-        out.append(dict(kernel=f"Gram {dt} {bx}x{by} (FP64 MFMA, incl. the partial reduction)", n=n,
-                        ms=ms, bytes=nbytes, flops=flops, **rf))
+        name = f"Gram {dt} {bx}x{by} (FP64 MFMA, incl. the partial reduction)"
+        if name.startswith(DOMINANT_KERNEL_PROBE) and DOMINANT_KERNEL_TRAFFIC_SRC == kernels_source_sha():
+            rf["traffic"] = DOMINANT_KERNEL_TRAFFIC
+        out.append(dict(kernel=name, n=n, ms=ms, bytes=nbytes, flops=flops, **rf))
         del X, Y
     torch.cuda.empty_cache()
     return out
