@@ -1610,9 +1610,9 @@ static void launch_update_pipe(hipStream_t st, const UpdArgs<T> &a, int kpad) {
     const int64_t waves = (a.n + rows - 1) / rows;
     // workgroups in flight, by measurement at 4096000 rows: 4096 for up to 4
     // slabs per row group (16 -> 16 complex64 with beta = 1: 417 -> 299 us
-    // against update_mfma_kernel), fewer for the wider ones whose register
+    // against update_mfma_kernel), 2048 for the wider ones whose register
     // buffers are larger
-    const int cap = SMAX <= 4 ? 4096 : (sizeof(T) == 8 ? 1024 : 2048);
+    const int cap = SMAX <= 4 ? 4096 : 2048;
     const int grid = (int)std::min<int64_t>((waves + 3) / 4, cap);
     // outputs larger than the last-level caches stream past them
     const int nts = (double)a.n * a.wout * sizeof(T) > 256.0 * 1024 * 1024;
@@ -1652,9 +1652,13 @@ static bool update_pipe(const UpdArgs<T> &a, int kpad, hipStream_t st) {
     }
     const int nt = (a.wout + 7) / 8;
     if constexpr (sizeof(T) == 8) {
+        // complex64 rows are half as long: two 16-row tiles per row group up
+        // to 4 slabs; from 5 slabs the register buffers of two tiles leave one
+        // wave per SIMD, and one tile per group is faster (48 + 16 -> 16 at
+        // 4096000 rows: 651 -> 551 us)
         switch (nt) {
-            case 1: return update_pipe_shape<T, 2, 1>(st, a, kpad);
-            case 2: return update_pipe_shape<T, 2, 2>(st, a, kpad);
+            case 1: return kpad > 32 ? update_pipe_shape<T, 1, 1>(st, a, kpad) : update_pipe_shape<T, 2, 1>(st, a, kpad);
+            case 2: return kpad > 32 ? update_pipe_shape<T, 1, 2>(st, a, kpad) : update_pipe_shape<T, 2, 2>(st, a, kpad);
             case 3: return update_pipe_shape<T, 1, 3>(st, a, kpad);
             case 4: return update_pipe_shape<T, 1, 4>(st, a, kpad);
             case 5: return update_pipe_shape<T, 1, 5>(st, a, kpad);
