@@ -844,7 +844,7 @@ void gram_lds_kernel(GramLArgs<T> a) {
 // are added in LDS in a fixed order, so the result is reproducible bit for bit.
 __global__ __launch_bounds__(256) void reduce_real_partials_kernel(const double *part, int nblk,
                                                                   int bx, int by, double2 *out,
-                                                                  int ldo) {
+                                                                  int ldo, int ctrans) {
     __shared__ double sh[8][32];
     const int nbx = 2 * bx;
     const int64_t E = (int64_t)nbx * 2 * by;
@@ -871,7 +871,9 @@ __global__ __launch_bounds__(256) void reduce_real_partials_kernel(const double 
         // real column 2q: rows 2p (rr) and 2p + 1 (ir); column 2q + 1: ri, ii
         const double rr = sh[0][2 * t], ir = sh[0][2 * t + 1];
         const double ri = sh[0][16 + 2 * t], ii = sh[0][16 + 2 * t + 1];
-        out[p0 + t + (int64_t)q * ldo] = make_double2(rr + ii, ri - ir);
+        // ctrans: the partials are of the swapped product, G(q, p) = conj of this
+        if (ctrans) out[q + (int64_t)(p0 + t) * ldo] = make_double2(rr + ii, ir - ri);
+        else out[p0 + t + (int64_t)q * ldo] = make_double2(rr + ii, ri - ir);
     }
 }
 
@@ -903,7 +905,7 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
 
 template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1, bool F32 = false>
 static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
-                                int ldo, int nblk_want) {
+                                int ldo, int nblk_want, int ctrans = 0) {
     a.G = (a.NT + NTC - 1) / NTC;
     if (a.G == 3) a.G = 4;
     if (a.MT > MTC || a.G > 4) throw Error(-1, "gram: no tile layout for this shape");
@@ -921,12 +923,13 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC, F32>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(((a.bx + 7) / 8) * a.by), dim3(256), 0, st,
-                       a.part, a.nblk, a.bx, a.by, out, ldo);
+                       a.part, a.nblk, a.bx, a.by, out, ldo, ctrans);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
 template <typename T>
-static void gram_launch_lds(hipStream_t st, const GramMArgs<T> &m, size_t part_cap, double2 *out, int ldo) {
+static void gram_launch_lds(hipStream_t st, const GramMArgs<T> &m, size_t part_cap, double2 *out, int ldo,
+                            int ctrans = 0) {
     constexpr int MTC = 8, NTC = 2, XTC = 8, YTC = 8, RCH = 16;
     GramLArgs<T> a{};
     a.n = m.n; a.X = m.X; a.ldx = m.ldx; a.bx = m.bx; a.Y = m.Y; a.ldy = m.ldy; a.by = m.by;
@@ -946,7 +949,7 @@ static void gram_launch_lds(hipStream_t st, const GramMArgs<T> &m, size_t part_c
     hipLaunchKernelGGL((gram_lds_kernel<T, MTC, NTC, XTC, YTC, RCH>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(((a.bx + 7) / 8) * a.by), dim3(256), 0, st,
-                       a.part, a.nblk, a.bx, a.by, out, ldo);
+                       a.part, a.nblk, a.bx, a.by, out, ldo, ctrans);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
@@ -956,6 +959,23 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
                              double2 *out, int ldo) {
     if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
     if (n <= 0) throw Error(-1, "gram: empty block");
+    // X at most 16 columns against a wider Y (no row scale): the product is
+    // formed as Y^H X, whose narrow side is the one the tile sets are built
+    // for, and written conjugate-transposed (16 x 48 at 4096000 rows: the
+    // direct form runs a third of its M tiles on zeros)
+    if (!yscale && bx <= 16 && by > 16 && !F32 && n >= ((int64_t)1 << 20)) {
+        GramMArgs<T> a{};
+        a.n = n; a.X = Y; a.ldx = ldy; a.bx = by; a.Y = X; a.ldy = ldx; a.by = bx;
+        a.part = reinterpret_cast<double *>(part);
+        a.MT = (2 * by + 15) / 16;
+        a.NT = (2 * bx + 15) / 16;
+        if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1, false>(st, a, part_cap, out, ldo, 256, 1);
+        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1, false>(st, a, part_cap, out, ldo, 256, 1);
+        else if (a.MT == 5) gram_launch_variant<T, 5, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
+        else if (a.MT == 6) gram_launch_variant<T, 6, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
+        else gram_launch_variant<T, 8, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
+        return;
+    }
     GramMArgs<T> a{};
     a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
     a.yscale = yscale;
@@ -2181,14 +2201,29 @@ __global__ __launch_bounds__(256) void resid_mfma_kernel(ResidArgs<T> a) {
             double2 x = to_d(bx[p][h]);
             if (t == 1 && scale1) x = cmul(to_d(brs[p]), x);
             if (col0 + h >= b) x = make_double2(0.0, 0.0);
+            // C V (t = 0) has zero coefficients for the B x columns: its
+            // slabs run only the A x tiles (one branch per slab, none per MFMA)
+            if (t == 0) {
 #pragma unroll
-            for (int part = 0; part < 2; ++part) {
-                const double av = part == 0 ? x.x : x.y;
+                for (int part = 0; part < 2; ++part) {
+                    const double av = part == 0 ? x.x : x.y;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const double bv =
-                        part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
-                    acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
+                    for (int nt = 0; nt < NT / 2; ++nt) {
+                        const double bv =
+                            part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
+                        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    const double av = part == 0 ? x.x : x.y;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const double bv =
+                            part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
+                        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
+                    }
                 }
             }
         }

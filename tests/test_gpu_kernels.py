@@ -211,11 +211,14 @@ def test_gram_of_one_block(device, w, dtype):
         assert np.max(np.abs(Gs - ref) / (np.abs(X).T @ np.abs(X))) < 1e-13
 
 
-@pytest.mark.parametrize("bx,by", [(64, 64), (48, 48), (32, 32), (64, 16), (40, 16), (48, 10), (40, 40)])
+@pytest.mark.parametrize("bx,by", [(64, 64), (48, 48), (32, 32), (64, 16), (40, 16), (48, 10), (40, 40),
+                                   (64, 48), (16, 48), (10, 40), (16, 64), (16, 17)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_gram_tall_blocks(device, bx, by, dtype):
     # from 2^20 rows the wide tile sets run in their two-waves-per-SIMD build
-    # with 512 blocks; a ragged row count past the threshold
+    # with 512 blocks, Y wider than 32 columns against wide X in the
+    # LDS-staged kernel, and X of at most 16 columns against a wider Y as the
+    # conjugate transpose of Y^H X; a ragged row count past the threshold
     import torch
     from paper_1506_06829_amd import gplhr as G
     n = (1 << 20) + 37
