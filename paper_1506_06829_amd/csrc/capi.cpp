@@ -479,18 +479,24 @@ void jacobi_apply(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp, con
         gplhr::launch_scale_rows<T>(st, n, b, R, ldr, dw, Y, ldy);
         return;
     }
-    T *J[2] = {static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st)), nullptr};
-    if (sweeps > 2) J[1] = static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st));
-    gplhr::launch_scale_rows<T>(st, n, b, R, ldr, dw, J[0], b);
-    int cur = 0;
+    // w_1 and w_2 in one pass (mode 2), then one pass per further sweep
+    T *J[2] = {nullptr, nullptr};
+    if (sweeps > 2) J[0] = static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st));
+    if (sweeps > 3) J[1] = static_cast<T *>(gplhr::dev_alloc(sizeof(T) * n * b, st));
+    int cur = -1;
     for (int t = 1; t < sweeps; ++t) {
         const bool last = (t == sweeps - 1);
-        T *o = last ? Y : J[1 - cur];
-        gplhr::launch_spmm<T>(st, n, rp, ci, val, J[cur], b, o, last ? ldy : b, b, 1, R, ldr, dw,
-                              plane, nnz);
-        cur = 1 - cur;
+        const int nxt = cur == 0 ? 1 : 0;
+        T *o = last ? Y : J[nxt];
+        if (t == 1)
+            gplhr::launch_spmm<T>(st, n, rp, ci, val, R, ldr, o, last ? ldy : b, b, 2, R, ldr, dw,
+                                  plane, nnz);
+        else
+            gplhr::launch_spmm<T>(st, n, rp, ci, val, J[cur], b, o, last ? ldy : b, b, 1, R, ldr, dw,
+                                  plane, nnz);
+        cur = nxt;
     }
-    gplhr::dev_free(J[0], st);
+    if (J[0]) gplhr::dev_free(J[0], st);
     if (J[1]) gplhr::dev_free(J[1], st);
 }
 }  // namespace

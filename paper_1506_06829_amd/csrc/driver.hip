@@ -196,7 +196,7 @@ void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int wc, int mode, const T *
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
-                  (double)n * wc * sizeof(T) * (mode == 0 ? 2 : 3);
+                  (double)n * wc * sizeof(T) * (mode == 1 ? 3 : 2);
 }
 
 template <typename T>
@@ -254,12 +254,14 @@ void Ctx::apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int wc) 
             launch_scale_rows<T>(st, n, wc, in, ldi, w.dw, dest, ldd);
             return;
         }
-        launch_scale_rows<T>(st, n, wc, in, ldi, w.dw, w.J1, b);
-        T *cur = w.J1;
+        // w_1 and w_2 in one pass (SpMM mode 2 forms w_1 = dw .* r at the
+        // gathered rows), then one pass per further sweep
+        T *cur = nullptr;
         for (int t = 1; t < pre.sweeps; ++t) {
             const bool last = (t == pre.sweeps - 1);
             T *o = last ? dest : (cur == w.J1 ? w.J2 : w.J1);
-            spmm_c<T>(cur, b, o, last ? ldd : b, wc, 1, in, ldi);
+            if (t == 1) spmm_c<T>(in, ldi, o, last ? ldd : b, wc, 2, in, ldi);
+            else spmm_c<T>(cur, b, o, last ? ldd : b, wc, 1, in, ldi);
             cur = o;
         }
     }

@@ -37,7 +37,9 @@ void pinned_free(void *p, size_t bytes);
 // ---------------------------------------------------------------------------
 
 // Y = C X (mode 0) or, for the damped Jacobi sweep, Y = X + dw .* (Rhs - C X)
-// (mode 1), where dw holds omega / C(i,i) per row.  plane > 0 runs the rows
+// (mode 1), where dw holds omega / C(i,i) per row; mode 2 is the first two
+// sweeps from zero, Y = w + dw .* (Rhs - C w) with w = dw .* Rhs, and takes X
+// = Rhs (ldx = ldr).  plane > 0 runs the rows
 // in the plane-slab order (plane rows per plane; must divide n and be a
 // multiple of 8), 0 in natural order; the result is the same.  nnz (the
 // stored entries, rp[n]) sets how many entries of a row are gathered at once;

@@ -147,8 +147,11 @@ struct SpmmArgs {
     int nt;         // 1: non-temporal stores of Y
 };
 
-// MODE 0: Y = C X; MODE 1: the damped Jacobi sweep (compile-time, so the plain
-// product carries no epilogue registers).  BATCH entries of a row have their
+// MODE 0: Y = C X; MODE 1: the damped Jacobi sweep Y = X + dw .* (Rhs - C X);
+// MODE 2: the first two sweeps from w_0 = 0 in one pass, Y = w + dw .* (Rhs -
+// C w) with w = dw .* Rhs formed on the fly (X is Rhs: every gathered row is
+// scaled by its own dw).  Compile-time, so the plain product carries no
+// epilogue registers.  BATCH entries of a row have their
 // block-row gathers in flight together.
 //
 // Index/value stream through LDS: when the rows of a workgroup are
@@ -215,6 +218,11 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
         load_vec<T, CPL>(a.X + row * a.ldx + c0, xo);
         load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
         w = a.dw[row];
+    } else if constexpr (MODE == 2) {
+        load_vec<T, CPL>(a.Rhs + row * a.ldr + c0, rh);
+        w = a.dw[row];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) xo[c] = cmul(w, rh[c]);
     }
     T acc[CPL];
 #pragma unroll
@@ -232,6 +240,16 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) x[u][c] = czero<T>();
             }
+        }
+        if constexpr (MODE == 2) {
+            // w_1 at the gathered rows: dw_j .* X_j (an empty slot reads row 0)
+            T s[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) s[u] = a.dw[j[u] >= 0 ? j[u] : 0];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u)
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) x[u][c] = cmul(s[u], x[u][c]);
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u)
@@ -333,7 +351,7 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
     a.nt = ((double)n * b * sizeof(T) > 256.0 * 1024 * 1024) ? 1 : 0;
     // lanes move 32 bytes of the block row: 4 complex64 or 2 complex128 values
     const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
-                            (mode == 1 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
+                            (mode != 0 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
     int cpl = 1;
     if constexpr (sizeof(T) == 8) {
         const bool ok4 = (b % 4 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) &&
@@ -362,7 +380,8 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
     const int64_t row_len = nnz > 0 ? (nnz + n - 1) / n : 0;
     const int rl = (int)std::min<int64_t>(row_len, 1 << 20);
     if (mode == 0) spmm_batch<T, 0>(st, a, cpl, grid, rl);
-    else spmm_batch<T, 1>(st, a, cpl, grid, rl);
+    else if (mode == 1) spmm_batch<T, 1>(st, a, cpl, grid, rl);
+    else spmm_batch<T, 2>(st, a, cpl, grid, rl);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
@@ -1414,11 +1433,11 @@ static void launch_lds_kernel(K kernel, int grid, size_t shmem, hipStream_t st, 
 }
 
 // Pipelined MFMA kernel for the streaming shapes (inputs at most 64 complex
-// columns, no row scaling).  A wavefront owns row groups of 16 MT rows, as in
-// update_mfma_kernel, but loads all S slabs of its next row group, and that
-// group's Out rows when beta != 0, into a second register buffer while it
-// multiplies the current one, so a whole row group's reads are in flight
-// behind every multiply.  The product tile then passes through a
+// columns, at most one row-scale vector).  A wavefront owns row groups of 16
+// MT rows, as in update_mfma_kernel, but loads all S slabs of its next row
+// group, and that group's Out rows when beta != 0, into a second register
+// buffer while it multiplies the current one, so a whole row group's reads are
+// in flight behind every multiply.  The product tile then passes through a
 // wave-private LDS tile and leaves as coalesced 16-byte chunks of Out rows
 // (one complex128 or two complex64 per lane), read-modify-write included.
 // Complex64 blocks need even widths, leading dimensions and column offsets
@@ -1484,7 +1503,20 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
     const T beta = from_d<T>(a.beta);
     T bx[2][SMAX][MT][2];
     C bd[2][BETA ? NCH : 1];
+    // the row scale of the terms that carry one (the launcher admits a single
+    // scale vector), loaded with the row group
+    const T *rsc = nullptr;
+    for (int t = 0; t < a.nterms; ++t)
+        if (a.t[t].rowscale) rsc = a.t[t].rowscale;
+    T brs[2][MT];
     auto load = [&](int p, int64_t g) {
+        if (rsc) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int64_t row = g + mt * 16 + li;
+                brs[p][mt] = rsc[row < a.n ? row : a.n - 1];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < SMAX; ++i) {
             if (i < nslab) {
@@ -1538,6 +1570,13 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) m[nt] = mrow[h * WOP + nt * 8];
                     const bool ok = col0 + h < tm.w;
+                    const bool scaled = tm.rowscale != nullptr;
+                    T xs[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const T x = bx[p][i][mt][h];
+                        xs[mt] = scaled ? cmul(brs[p][mt], x) : x;
+                    }
 #pragma unroll
                     for (int part = 0; part < 2; ++part) {
                         R bv[NT];
@@ -1546,7 +1585,7 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
                             bv[nt] = part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) {
-                            const T x = bx[p][i][mt][h];
+                            const T x = xs[mt];
                             const R av = ok ? (part == 0 ? x.x : x.y) : (R)0;
 #pragma unroll
                             for (int nt = 0; nt < NT; ++nt)
@@ -1660,9 +1699,15 @@ static bool update_pipe(const UpdArgs<T> &a, int kpad, hipStream_t st) {
     if (a.nterms < 1 || kpad < 8 || kpad > 64) return false;
     auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     if (!al16(a.out) || (a.add && !al16(a.add))) return false;
+    const void *rs = nullptr;
     for (int t = 0; t < a.nterms; ++t) {
         const UpdTerm<T> &tm = a.t[t];
-        if (tm.rowscale || !al16(tm.in)) return false;
+        // one row-scale vector at most (the kernel holds one per row group)
+        if (tm.rowscale) {
+            if (rs && rs != tm.rowscale) return false;
+            rs = tm.rowscale;
+        }
+        if (!al16(tm.in)) return false;
         if (sizeof(T) == 8 && ((tm.ld | tm.col | tm.w) & 1)) return false;
     }
     if (sizeof(T) == 8) {
