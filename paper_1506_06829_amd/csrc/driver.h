@@ -136,7 +136,7 @@ struct Ctx {
     template <typename T> Work<T> &W();
     template <typename T>
     void gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
-              double2 *out, bool f32 = false);
+              double2 *out);
     template <typename T>
     void update(T *out, int ldo, int wout, int ocol, int split, int ocol2, bool beta1, int nterms,
                 const UpdTerm<T> *terms, const T *add = nullptr, int ldadd = 0);

@@ -111,9 +111,9 @@ template <> Work<float2> &Ctx::W<float2>() { return wf; }
 // ---------------------------------------------------------------------------
 template <typename T>
 void Ctx::gram(const T *X, int ldx, int bx, const T *Y, int ldy, int by, const T *yscale,
-               double2 *out, bool f32) {
+               double2 *out) {
     tbegin(T_GRAM);
-    launch_gram<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_CAP, out, bx, f32);
+    launch_gram<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, PART_CAP, out, bx);
     tend(T_GRAM);
 }
 
@@ -1077,7 +1077,7 @@ template void Ctx::update<double2>(double2 *, int, int, int, int, int, bool, int
 }  // namespace gplhr
 namespace gplhr {
 template void Ctx::gram<double2>(const double2 *, int, int, const double2 *, int, int,
-                                 const double2 *, double2 *, bool);
+                                 const double2 *, double2 *);
 template void Ctx::gram<float2>(const float2 *, int, int, const float2 *, int, int, const float2 *,
-                                double2 *, bool);
+                                double2 *);
 }  // namespace gplhr

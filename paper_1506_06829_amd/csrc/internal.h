@@ -55,13 +55,10 @@ int spmm_plane(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci);
 
 // G = X^H diag(yscale) Y (bx-by-by, FP64 accumulation, fixed reduction order)
 // written column-major with leading dimension ldo.  yscale (complex per row)
-// may be null.  `part` is scratch of part_cap complex128 entries.  f32 (for
-// complex64 operands; ignored for complex128): products on the FP32 MFMA,
-// summed in FP32 over a few rows per wave and in FP64 beyond that.
+// may be null.  `part` is scratch of part_cap complex128 entries.
 template <typename T>
 void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
-                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo,
-                 bool f32 = false);
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo);
 
 // out[p + q*ldo] = sum_blk part[(p + q*bx) * nblk + blk]  (fixed order)
 void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,

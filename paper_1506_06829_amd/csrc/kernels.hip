@@ -473,16 +473,11 @@ constexpr int GM_PF = 4;   // K steps in flight per wave
 
 // OCC: waves per SIMD the register allocation must leave room for (1: the
 // compiler's choice; 2: at most 256 VGPRs + AGPRs per lane).
-// F32 (complex64 operands only): the products run on the FP32 MFMA
-// (v_mfma_f32_16x16x4f32) and accumulate in FP32 over the PF K steps of one
-// round (4 PF rows per wave), after which the FP32 tile is added to an FP64
-// accumulator; everything across rounds, waves and blocks is FP64.
-template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1, bool F32 = false>
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, 8)))
 void gram_mfma_kernel(GramMArgs<T> a) {
     using R = typename RealOf<T>::R;
-    static_assert(!F32 || sizeof(T) == 8, "the FP32 MFMA build is for complex64 operands");
-    using OpR = typename std::conditional<F32, float, double>::type;
+    using OpR = double;
     __shared__ double red[2 * MTC * NTC * 256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = wave % a.G, h = wave / a.G;
@@ -492,17 +487,10 @@ void gram_mfma_kernel(GramMArgs<T> a) {
     // a wave whose column group lies past the Gram's last N tile has nothing to do
     const bool active = h < a.ks && nt0 < a.NT;
     d4v acc[MTC][NTC];
-    f4v acc32[F32 ? MTC : 1][F32 ? NTC : 1];
 #pragma unroll
     for (int mt = 0; mt < MTC; ++mt)
 #pragma unroll
         for (int t = 0; t < NTC; ++t) acc[mt][t] = d4v{0.0, 0.0, 0.0, 0.0};
-    if constexpr (F32) {
-#pragma unroll
-        for (int mt = 0; mt < MTC; ++mt)
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) acc32[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
-    }
     const int64_t rb = (int64_t)blockIdx.x * a.rows_per_blk;
     const int64_t re = min(a.n, rb + a.rows_per_blk);
     const int64_t step = 4LL * a.ks;
@@ -568,37 +556,20 @@ void gram_mfma_kernel(GramMArgs<T> a) {
 #pragma unroll
                 for (int mt = 0; mt < MTC; ++mt) {
 #pragma unroll
-                    for (int t = 0; t < NTC; ++t) {
-                        if constexpr (F32)
-                            acc32[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                xv[mt], yv[t], acc32[mt][t], 0, 0, 0);
-                        else
-                            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                xv[mt], yv[t], acc[mt][t], 0, 0, 0);
-                    }
+                    for (int t = 0; t < NTC; ++t)
+                        acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[mt], yv[t], acc[mt][t], 0, 0, 0);
                 }
                 load(p, r + (int64_t)(j + p + PF) * step);
             }
-            if constexpr (F32) {
-                // end of a round: the FP32 tiles go into the FP64 accumulators
-#pragma unroll
-                for (int mt = 0; mt < MTC; ++mt)
-#pragma unroll
-                    for (int t = 0; t < NTC; ++t) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[mt][t][v] += (double)acc32[mt][t][v];
-                        acc32[mt][t] = f4v{0.f, 0.f, 0.f, 0.f};
-                    }
-            }
         }
     }
-    // D(i, j) of a 16x16 tile on gfx950: register v of lane l holds j = l % 16
-    // and i = 4 v + l / 16 (FP64 16x16x4) or i = 4 (l / 16) + v (FP32 16x16x4)
+    // D(i, j) of a 16x16 tile on gfx950 (FP64 16x16x4): register v of lane l
+    // holds j = l % 16 and i = 4 v + l / 16
     auto store = [&](int mt, int nt, const d4v &d) {
         const int jj = nt * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int i = mt * 16 + (F32 ? 4 * lk + v : 4 * v + lk);
+            const int i = mt * 16 + 4 * v + lk;
             // block-contiguous partials: this block's nbx-by-nby real Gram
             if (i < nbx && jj < nby)
                 a.part[(int64_t)blockIdx.x * nbx * nby + i + (int64_t)jj * nbx] = d[v];
@@ -922,7 +893,7 @@ void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int b
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1, bool F32 = false>
+template <typename T, int MTC, int NTC, int PF = GM_PF, int OCC = 1>
 static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap, double2 *out,
                                 int ldo, int nblk_want, int ctrans = 0) {
     a.G = (a.NT + NTC - 1) / NTC;
@@ -939,7 +910,7 @@ static void gram_launch_variant(hipStream_t st, GramMArgs<T> a, size_t part_cap,
     a.rows_per_blk = ((a.n + nblk - 1) / nblk + step - 1) / step * step;
     // no block starts past the last row
     a.nblk = (int)((a.n + a.rows_per_blk - 1) / a.rows_per_blk);
-    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC, F32>), dim3(a.nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((gram_mfma_kernel<T, MTC, NTC, PF, OCC>), dim3(a.nblk), dim3(256), 0, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(reduce_real_partials_kernel, dim3(((a.bx + 7) / 8) * a.by), dim3(256), 0, st,
                        a.part, a.nblk, a.bx, a.by, out, ldo, ctrans);
@@ -972,7 +943,7 @@ static void gram_launch_lds(hipStream_t st, const GramMArgs<T> &m, size_t part_c
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
-template <typename T, bool F32>
+template <typename T>
 static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
                              int ldy, int by, const T *yscale, double2 *part, size_t part_cap,
                              double2 *out, int ldo) {
@@ -982,17 +953,17 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
     // formed as Y^H X, whose narrow side is the one the tile sets are built
     // for, and written conjugate-transposed (16 x 48 at 4096000 rows: the
     // direct form runs a third of its M tiles on zeros)
-    if (!yscale && bx <= 16 && by > 16 && !F32 && n >= ((int64_t)1 << 20)) {
+    if (!yscale && bx <= 16 && by > 16 && n >= ((int64_t)1 << 20)) {
         GramMArgs<T> a{};
         a.n = n; a.X = Y; a.ldx = ldy; a.bx = by; a.Y = X; a.ldy = ldx; a.by = bx;
         a.part = reinterpret_cast<double *>(part);
         a.MT = (2 * by + 15) / 16;
         a.NT = (2 * bx + 15) / 16;
-        if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1, false>(st, a, part_cap, out, ldo, 256, 1);
-        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1, false>(st, a, part_cap, out, ldo, 256, 1);
-        else if (a.MT == 5) gram_launch_variant<T, 5, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
-        else if (a.MT == 6) gram_launch_variant<T, 6, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
-        else gram_launch_variant<T, 8, 2, 2, 2, false>(st, a, part_cap, out, ldo, 512, 1);
+        if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1>(st, a, part_cap, out, ldo, 256, 1);
+        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1>(st, a, part_cap, out, ldo, 256, 1);
+        else if (a.MT == 5) gram_launch_variant<T, 5, 2, 2, 2>(st, a, part_cap, out, ldo, 512, 1);
+        else if (a.MT == 6) gram_launch_variant<T, 6, 2, 2, 2>(st, a, part_cap, out, ldo, 512, 1);
+        else gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512, 1);
         return;
     }
     GramMArgs<T> a{};
@@ -1017,54 +988,47 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
         // test basis): MT x 2 tiles per wave, rows split over the 4 waves; a
         // wider compiled tile set would only cost registers (4096000 rows:
         // 40 x 10 924 -> 633 us, 30 x 10 686 -> 526 us)
-        if (a.MT <= 2) gram_launch_variant<T, 2, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        if (a.MT <= 2) gram_launch_variant<T, 2, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
+        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         else if (a.MT == 5) {
-            if (tall) gram_launch_variant<T, 5, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 5, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 5, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 5, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         } else if (a.MT == 6) {
-            if (tall) gram_launch_variant<T, 6, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 6, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 6, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 6, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         } else {
-            if (tall) gram_launch_variant<T, 8, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-            else gram_launch_variant<T, 8, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+            if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+            else gram_launch_variant<T, 8, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         }
     } else if (a.MT <= 3)
-        gram_launch_variant<T, 3, 3, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        gram_launch_variant<T, 3, 3, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4) {
-        if (tall) gram_launch_variant<T, 4, 4, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 4, 4, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        if (tall) gram_launch_variant<T, 4, 4, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 4, 4, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     } else if (a.MT == 5)   // two K steps in flight: more would spill registers
-        gram_launch_variant<T, 5, 5, 2, 1, F32>(st, a, part_cap, out, ldo, nb);
+        gram_launch_variant<T, 5, 5, 2, 1>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 6) {
-        if (tall) gram_launch_variant<T, 6, 3, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 6, 3, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        if (tall) gram_launch_variant<T, 6, 3, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 6, 3, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     } else {
         // (Y wider than 32 columns: at 64 x 32 the register-streaming kernel
         // measured faster, 1219 against 1320 us for complex64)
-        if (tall && !F32 && a.NT > 4) gram_launch_lds<T>(st, a, part_cap, out, ldo);
-        else if (tall) gram_launch_variant<T, 8, 2, 2, 2, F32>(st, a, part_cap, out, ldo, 512);
-        else gram_launch_variant<T, 8, 2, GM_PF, 1, F32>(st, a, part_cap, out, ldo, nb);
+        if (tall && a.NT > 4) gram_launch_lds<T>(st, a, part_cap, out, ldo);
+        else if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 8, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     }
 }
 template <typename T>
 void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
-                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo,
-                 bool f32) {
-    if constexpr (sizeof(T) == 8) {
-        if (f32) {
-            launch_gram_impl<T, true>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
-            return;
-        }
-    }
-    launch_gram_impl<T, false>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
+                 int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo) {
+    launch_gram_impl<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
 }
 template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
                                    const double2 *, int, int, const double2 *, double2 *, size_t,
-                                   double2 *, int, bool);
+                                   double2 *, int);
 template void launch_gram<float2>(hipStream_t, int64_t, const float2 *, int, int, const float2 *,
-                                  int, int, const float2 *, double2 *, size_t, double2 *, int, bool);
+                                  int, int, const float2 *, double2 *, size_t, double2 *, int);
 
 // ---------------------------------------------------------------------------
 // row-local block update
