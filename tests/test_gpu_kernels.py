@@ -212,7 +212,7 @@ def test_gram_of_one_block(device, w, dtype):
 
 
 @pytest.mark.parametrize("bx,by", [(64, 64), (48, 48), (32, 32), (64, 16), (40, 16), (48, 10), (40, 40),
-                                   (64, 48), (16, 48), (10, 40), (16, 64), (16, 17)])
+                                   (64, 48), (16, 48), (10, 40), (16, 64), (16, 17), (56, 40), (64, 33)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_gram_tall_blocks(device, bx, by, dtype):
     # from 2^20 rows the wide tile sets run in their two-waves-per-SIMD build
