@@ -264,6 +264,38 @@ def test_block_update_matches_definition(device, wx, wy, dtype, beta):
         assert np.array_equal(rest, Y0[:, wy:].astype(rest.dtype))
 
 
+@pytest.mark.parametrize("wx,wy", [(16, 16), (32, 16), (48, 16), (64, 16), (16, 48), (64, 32), (64, 48),
+                                   (8, 8), (40, 24), (6, 10), (2, 2)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("beta", [0.0, 1.0, 0.5 - 0.25j])
+def test_block_update_even_strides(device, wx, wy, dtype, beta):
+    # even widths and leading dimensions: the shapes the pipelined kernel
+    # takes for complex64 too (16-byte pairs and output chunks), with the
+    # output inside a wider block and rows in ragged counts
+    import torch
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(wx * 64 + wy + 7)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    for n in (1, 17, 1000, 100003):
+        X = _block(rng, n, wx, ld=wx + 4)
+        Y0 = _block(rng, n, wy, ld=wy + 6)
+        M = rng.standard_normal((wx, wy)) + 1j * rng.standard_normal((wx, wy))
+        if dtype == "c64":
+            X = X.astype(np.complex64).astype(np.complex128)
+            Y0 = Y0.astype(np.complex64).astype(np.complex128)
+        Xd = torch.as_tensor(X).to(device, tdt)[:, 2:wx + 2]
+        Yfull = torch.as_tensor(Y0).to(device, tdt)
+        Md = torch.as_tensor(M).to(device)
+        out = G.block_update(Xd, Md, Yfull[:, 4:wy + 4], beta=beta).cpu().numpy()
+        ref = beta * Y0[:, 4:wy + 4] + X[:, 2:wx + 2] @ M
+        scale = abs(beta) * np.abs(Y0[:, 4:wy + 4]) + np.abs(X[:, 2:wx + 2]) @ np.abs(M)
+        tol = 1e-14 if dtype == "c128" else 3e-6
+        assert np.max(np.abs(out - ref) / scale) < tol, (n, wx, wy)
+        rest = Yfull.cpu().numpy()
+        assert np.array_equal(rest[:, :4], Y0[:, :4].astype(rest.dtype))
+        assert np.array_equal(rest[:, wy + 4:], Y0[:, wy + 4:].astype(rest.dtype))
+
+
 @pytest.mark.parametrize("w", [10, 16, 48])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_block_update_in_place(device, w, dtype):
