@@ -341,6 +341,31 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
 gplhr_status gplhr_block_copy(int dtype, int64_t n, const void *X, int ldx, void *Y, int ldy, int w,
                               void *hip_stream);
 
+/* Z(:, wy:wy+w) <- orth((I - Y Y^H) Z(:, wy:wy+w)) for Y = Z(:, 0:wy) with
+ * orthonormal columns (wy = 0: orthonormalisation alone): the block
+ * Gram-Schmidt projection and orthonormalisation with which Algorithm 2 builds
+ * its trial and test bases (Sections 3.3 to 3.5; the paper leaves the
+ * orthonormalisation procedure open).  Each of `passes` passes (1..3) is one
+ * FP64 Gram [Y X]^H X, the Cholesky factor R of the projected block's Gram
+ * X^H X - (Y^H X)^H (Y^H X), and the row-local update
+ * X <- (X - Y (Y^H X)) R^{-1}; all passes but the last only project a block
+ * whose projection cancels almost all of a column.  Two passes give columns
+ * orthonormal and orthogonal to Y to working precision when the projected
+ * block is well conditioned; the result is then the Q of the QR factorisation
+ * of (I - Y Y^H) X whose R has a positive real diagonal.  Z is a row-major
+ * device block (ld >= wy + w) of dtype 0 (complex128) or 1 (complex64: FP32
+ * products, FP64 Grams and factors); the solver's own kernels.  Allocates its
+ * scratch on the stream and waits for the result before returning.
+ * A column that lies in span(Y) to working precision is only projected by the
+ * first pass and comes back, from the second, as a unit vector of its
+ * rounding residual, orthogonal to Y and to the other columns.
+ * 1 <= w <= 48, 0 <= wy <= 48, wy + w <= 64; returns ARG otherwise, and
+ * BREAKDOWN when a Cholesky pivot of the projected block vanished (columns of
+ * the block itself are linearly dependent to working precision; the columns
+ * written are then not orthonormal). */
+gplhr_status gplhr_proj_orth(int dtype, int64_t n, void *Z, int ld, int wy, int w, int passes,
+                             void *hip_stream);
+
 /* The same G = X^H Y as gplhr_gram, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): it calls no allocating routine.  Its partial sums go to a

@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "driver.h"
@@ -384,6 +385,48 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
                                        static_cast<const float2 *>(Y), ldy, by, nullptr, part, cap,
                                        static_cast<double2 *>(G), bx);
         GPLHR_HIP_CHECK(hipFreeAsync(part, st));
+        return 0;
+    });
+}
+
+gplhr_status gplhr_proj_orth(int dtype, int64_t n, void *Z, int ld, int wy, int w, int passes,
+                             void *hip_stream) {
+    return guard(nullptr, [&]() {
+        if (n < 1 || w < 1 || w > 48 || wy < 0 || wy > 48 || wy + w > 64 || ld < wy + w ||
+            passes < 1 || passes > 3 || (dtype != 0 && dtype != 1) || !Z)
+            throw gplhr::Error(-1, "gplhr_proj_orth: bad arguments");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int wg = wy + w;
+        // one allocation: Gram partials | G = [Y X]^H X | R^{-1} | C_Y | counter
+        const size_t cap = (size_t)1024 * wg * w;
+        const size_t nG = (size_t)wg * w, nR = (size_t)w * w, nC = (size_t)std::max(wy, 1) * w;
+        double2 *buf = nullptr;
+        GPLHR_HIP_CHECK(hipMallocAsync((void **)&buf, sizeof(double2) * (cap + nG + nR + nC + 1), st));
+        double2 *part = buf, *G = buf + cap, *rinv = G + nG, *cy = rinv + nR;
+        int *status = reinterpret_cast<int *>(cy + nC);
+        GPLHR_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int), st));
+        auto run = [&](auto *X) {
+            using T = std::remove_pointer_t<decltype(X)>;
+            for (int p = 0; p < passes; ++p) {
+                gplhr::launch_gram<T>(st, n, X, ld, wg, X + wy, ld, w, nullptr, part, cap, G, wg);
+                gplhr::launch_chol_proj(st, wy, w, G, rinv, cy, status, p + 1 < passes);
+                gplhr::UpdTerm<T> t[2];
+                t[0].in = X; t[0].ld = ld; t[0].col = wy; t[0].w = w; t[0].M = rinv; t[0].ldm = w;
+                t[0].upper = true;
+                t[1].in = X; t[1].ld = ld; t[1].col = 0; t[1].w = wy; t[1].M = cy; t[1].ldm = wy;
+                gplhr::launch_update<T>(st, n, X, ld, w, wy, w, 0, make_double2(0.0, 0.0),
+                                        wy > 0 ? 2 : 1, t);
+            }
+        };
+        if (dtype == 0) run(static_cast<double2 *>(Z));
+        else run(static_cast<float2 *>(Z));
+        int pivots = 0;
+        GPLHR_HIP_CHECK(hipMemcpyAsync(&pivots, status, sizeof(int), hipMemcpyDeviceToHost, st));
+        GPLHR_HIP_CHECK(hipFreeAsync(buf, st));
+        GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+        if (pivots > 0)
+            throw gplhr::Error(-4, "gplhr_proj_orth: a Cholesky pivot of the projected block vanished "
+                                   "(the block is rank deficient to working precision)");
         return 0;
     });
 }

@@ -155,7 +155,7 @@ void Ctx::cholqr(T *X, int ld, int col, int w, int passes, T *mir1, T *mir2) {
         gram<T>(X + col, ld, w, X + col, ld, w, nullptr, g0);
         launch_chol_rinv(st, w, g0, rinv, dstatus);
         UpdTerm<T> t;
-        t.in = X; t.ld = ld; t.col = col; t.w = w; t.M = rinv; t.ldm = w;
+        t.in = X; t.ld = ld; t.col = col; t.w = w; t.M = rinv; t.ldm = w; t.upper = true;
         update<T>(X, ld, w, col, w, 0, false, 1, &t);
         if (mir1) {
             t.in = mir1;
@@ -183,6 +183,7 @@ void Ctx::proj_orth(T *X, int ld, int ycol, int wy, int xcol, int w, int passes)
         launch_chol_proj(st, wy, w, g0, rinv, g1, dstatus, p + 1 < passes);
         UpdTerm<T> t[2];
         t[0].in = X; t[0].ld = ld; t[0].col = xcol; t[0].w = w; t[0].M = rinv; t[0].ldm = w;
+        t[0].upper = true;
         t[1].in = X; t[1].ld = ld; t[1].col = ycol; t[1].w = wy; t[1].M = g1; t[1].ldm = wy;
         update<T>(X, ld, w, xcol, w, 0, false, wy > 0 ? 2 : 1, t);
     }
@@ -294,7 +295,7 @@ void Ctx::apply_gmres(T *dest, int ldd, int dcol, int a) {
             gram<T>(G + col, lg, a, G + col, lg, a, nullptr, g0);
             launch_chol_rinv(st, a, g0, rinv, dstatus, slot(j, 2 + p));
             UpdTerm<T> t;
-            t.in = G; t.ld = lg; t.col = col; t.w = a; t.M = rinv; t.ldm = a;
+            t.in = G; t.ld = lg; t.col = col; t.w = a; t.M = rinv; t.ldm = a; t.upper = true;
             update<T>(G, lg, a, col, a, 0, false, 1, &t);
         }
     };
@@ -535,7 +536,7 @@ void Ctx::eig_orthonormalise() {
         gram<T>(w.Z, ld, b, w.Z, ld, b, nullptr, g0);
         launch_chol_rinv(st, b, g0, rinv, dstatus, g1 + p * bb);
         UpdTerm<T> t;
-        t.ld = ld; t.col = 0; t.w = b; t.M = rinv; t.ldm = b;
+        t.ld = ld; t.col = 0; t.w = b; t.M = rinv; t.ldm = b; t.upper = true;
         t.in = w.Z;  update<T>(w.Z, ld, b, 0, b, 0, false, 1, &t);
         t.in = w.CZ; update<T>(w.CZ, ld, b, 0, b, 0, false, 1, &t);
         if (bz) { t.in = bz; update<T>(bz, ld, b, 0, b, 0, false, 1, &t); }
@@ -643,6 +644,7 @@ void Ctx::iterate_once() {
         launch_chol_proj(st, b, wq, g0, rinv, g1, dstatus, true);
         UpdTerm<T> t[2];
         t[0].in = CZ; t[0].ld = ld; t[0].col = b; t[0].w = wq; t[0].M = rinv; t[0].ldm = wq;
+        t[0].upper = true;
         t[1].in = U; t[1].ld = ld; t[1].col = 0; t[1].w = b; t[1].M = g1; t[1].ldm = b;
         update<T>(U, ld, wq, b, wq, 0, false, 2, t);
     }

@@ -76,6 +76,7 @@ struct UpdTerm {
     int ldm = 0;
     double2 alpha = {1.0, 0.0};
     const T *rowscale = nullptr;
+    bool upper = false;   // M(k, j) = 0 for k > j (the caller guarantees it)
 };
 
 // Out(:, map(c)) = beta * Out(:, map(c)) + Add(:, c) + sum_t term_t(:, c),

@@ -1446,7 +1446,11 @@ struct UpdPipeShape {
 };
 
 // BETA: Out is read (beta != 0); without it no Out buffer is held.
-template <typename T, int MT, int NT, int SMAX, bool BETA>
+// TRI: the coefficients of term 0 are upper triangular (M(k, j) = 0 for
+// k > j, as R^{-1} of a Cholesky-QR step) and fill at least NT slabs, so the
+// products of its slab i with the output tiles nt < i are zero and are not
+// formed.
+template <typename T, int MT, int NT, int SMAX, bool BETA, bool TRI = false>
 __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad, int nslab, int nts) {
     using Sh = UpdPipeShape<T, MT, NT>;
     using R = typename UpdMma<T>::R;
@@ -1543,7 +1547,8 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
                 for (int h = 0; h < 2; ++h) {
                     T m[NT];
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) m[nt] = mrow[h * WOP + nt * 8];
+                    for (int nt = 0; nt < NT; ++nt)
+                        m[nt] = (TRI && i < NT && nt < i) ? czero<T>() : mrow[h * WOP + nt * 8];
                     const bool ok = col0 + h < tm.w;
                     const bool scaled = tm.rowscale != nullptr;
                     T xs[MT];
@@ -1564,7 +1569,8 @@ __global__ __launch_bounds__(256) void update_pipe_kernel(UpdArgs<T> a, int kpad
                             const R av = ok ? (part == 0 ? x.x : x.y) : (R)0;
 #pragma unroll
                             for (int nt = 0; nt < NT; ++nt)
-                                acc[mt][nt] = UpdMma<T>::mma(av, bv[nt], acc[mt][nt]);
+                                if (!(TRI && i < NT && nt < i))
+                                    acc[mt][nt] = UpdMma<T>::mma(av, bv[nt], acc[mt][nt]);
                         }
                     }
                 }
@@ -1651,6 +1657,16 @@ static void launch_update_pipe(hipStream_t st, const UpdArgs<T> &a, int kpad) {
     // outputs larger than the last-level caches stream past them
     const int nts = (double)a.n * a.wout * sizeof(T) > 256.0 * 1024 * 1024;
     const size_t shmem = UpdPipeShape<T, MT, NT>::shmem(kpad);
+    if constexpr (MT == 1 && NT == 6 && SMAX == 8) {
+        // the Cholesky-QR shape of the test basis (48 columns from their
+        // upper triangular R^{-1} and 16 more): 15 of the 36 products of the
+        // triangular term are zero
+        if (!beta && a.t[0].upper && pad8(a.t[0].w) >= 8 * NT) {
+            launch_lds_kernel(update_pipe_kernel<T, MT, NT, SMAX, false, true>, grid, shmem, st, a, kpad,
+                              kpad / 8, nts);
+            return;
+        }
+    }
     if (beta)
         launch_lds_kernel(update_pipe_kernel<T, MT, NT, SMAX, true>, grid, shmem, st, a, kpad, kpad / 8, nts);
     else

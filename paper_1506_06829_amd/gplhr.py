@@ -70,7 +70,7 @@ EXPORTS = ["gplhr_default_options", "gplhr_create", "gplhr_iterate", "gplhr_get_
            "gplhr_destroy",
            "gplhr_last_error", "gplhr_spmm", "gplhr_csr_plane", "gplhr_gram", "gplhr_jacobi",
            "gplhr_block_update", "gplhr_gram_noalloc", "gplhr_get_residual_norms",
-           "gplhr_block_copy"]
+           "gplhr_block_copy", "gplhr_proj_orth"]
 
 
 def lib():
@@ -122,6 +122,8 @@ def lib():
     L.gplhr_block_update.argtypes = [i32, i64, vp, i32, i32, vp, i32, vp, i32, i32,
                                      ctypes.c_double, ctypes.c_double, vp]
     L.gplhr_block_update.restype = i32
+    L.gplhr_proj_orth.argtypes = [i32, i64, vp, i32, i32, i32, i32, vp]
+    L.gplhr_proj_orth.restype = i32
     _lib = L
     return L
 
@@ -353,6 +355,17 @@ def block_update(X: torch.Tensor, M: torch.Tensor, Y: Optional[torch.Tensor] = N
                                     _ptr(Y), Y.stride(0), wy, beta.real, beta.imag,
                                     _stream_ptr()))
     return Y
+
+
+def proj_orth(Z: torch.Tensor, wy: int, w: int, passes: int = 2) -> torch.Tensor:
+    """Z[:, wy:wy+w] <- orth((I - Y Y^H) Z[:, wy:wy+w]) for the orthonormal
+    Y = Z[:, :wy], in place, with the library's Gram, Cholesky and update
+    kernels (Z complex128 or complex64, row-major with unit column stride)."""
+    dtype = {torch.complex128: 0, torch.complex64: 1}[Z.dtype]
+    assert Z.dim() == 2 and Z.stride(1) == 1 and Z.shape[1] >= wy + w
+    _check(lib().gplhr_proj_orth(dtype, Z.shape[0], _ptr(Z), Z.stride(0), wy, w, passes,
+                                 _stream_ptr()))
+    return Z
 
 
 def gram(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:

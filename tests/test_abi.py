@@ -77,6 +77,15 @@ def test_argument_errors_without_device_work():
     for wx, wy in [(0, 4), (129, 4), (4, 0), (4, 49)]:
         assert L.gplhr_block_update(0, 10, None, 200, wx, None, 200, None, 200, wy,
                                     ctypes.c_double(0.0), ctypes.c_double(0.0), None) == -1
+    # projection + Cholesky-QR: widths, passes, leading dimension, dtype, NULL block
+    for dt, n, ld, wy, w, passes in [(0, 10, 64, 0, 0, 2), (0, 10, 64, 0, 49, 2),
+                                     (0, 10, 64, 49, 8, 2), (0, 10, 64, 24, 48, 2),
+                                     (0, 10, 64, 16, 16, 0), (0, 10, 64, 16, 16, 4),
+                                     (0, 10, 31, 16, 16, 2), (2, 10, 64, 16, 16, 2),
+                                     (0, 0, 64, 16, 16, 2)]:
+        assert L.gplhr_proj_orth(dt, n, ctypes.c_void_p(16), ld, wy, w, passes, None) == -1
+    assert L.gplhr_proj_orth(0, 10, None, 64, 16, 16, 2, None) == -1
+    assert b"gplhr_proj_orth" in L.gplhr_last_error(None)
     assert L.gplhr_iterate(None, 1, None, None) == -1
 
 

@@ -317,6 +317,88 @@ def test_block_update_in_place(device, w, dtype):
     assert np.max(np.abs(Xd.cpu().numpy() - ref) / scale) < tol
 
 
+@pytest.mark.parametrize("wy,w", [(0, 16), (16, 16), (16, 48), (0, 48), (48, 16), (32, 32),
+                                  (10, 20), (3, 5), (24, 40), (8, 48)])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_proj_orth_matches_qr(device, wy, w, dtype):
+    # Z(:, wy:wy+w) <- orth((I - Y Y^H) X) in two passes: the Q of the QR
+    # factorisation of the projected block with a positive real diagonal (the
+    # oracle's orth); Y = Z(:, :wy) and the columns after the block are left
+    # as they were.  The 48-column blocks take the update path that skips the
+    # zero products of the triangular R^{-1}.
+    import torch
+    from oracle.gplhr_oracle import orth
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(100 * wy + w)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    for n in (257, 100003):
+        ld = wy + w + 2
+        Z = _block(rng, n, ld)
+        if wy:
+            Z[:, :wy] = orth(Z[:, :wy])
+            # a component along Y for the projection to remove
+            Z[:, wy:wy + w] += Z[:, :wy] @ (rng.standard_normal((wy, w)) + 1j * rng.standard_normal((wy, w)))
+        if dtype == "c64":
+            Z = Z.astype(np.complex64).astype(np.complex128)
+        Y, X = Z[:, :wy], Z[:, wy:wy + w]
+        ref = orth(X - Y @ (Y.conj().T @ X))
+        Zd = torch.as_tensor(Z).to(device, tdt)
+        G.proj_orth(Zd, wy, w, passes=2)
+        out = Zd.cpu().numpy().astype(np.complex128)
+        tol = 1e-12 if dtype == "c128" else 2e-5
+        err = np.linalg.norm(out[:, wy:wy + w] - ref) / np.sqrt(w)
+        assert err < tol, (n, wy, w, err)
+        Q = out[:, wy:wy + w]
+        assert np.max(np.abs(Q.conj().T @ Q - np.eye(w))) < (1e-13 if dtype == "c128" else 1e-5)
+        if wy:
+            assert np.max(np.abs(Y.conj().T @ Q)) < (1e-13 if dtype == "c128" else 1e-5)
+        assert np.array_equal(out[:, :wy], Z[:, :wy])
+        assert np.array_equal(out[:, wy + w:], Z[:, wy + w:])
+
+
+@pytest.mark.parametrize("wy", [0, 16])
+def test_proj_orth_reports_rank_deficiency(device, wy):
+    # a column that repeats another leaves a vanishing Cholesky pivot:
+    # BREAKDOWN, not a silent result
+    import torch
+    from oracle.gplhr_oracle import orth
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(5 + wy)
+    n, w = 4099, 16
+    Z = _block(rng, n, wy + w)
+    if wy:
+        Z[:, :wy] = orth(Z[:, :wy])
+    Z[:, wy + 7] = Z[:, wy + 2]
+    Zd = torch.as_tensor(Z).to(device)
+    with pytest.raises(Exception, match="rank deficient"):
+        G.proj_orth(Zd, wy, w, passes=2)
+
+
+def test_proj_orth_column_inside_span_y(device):
+    # a column inside span(Y): the first pass only projects (the cancellation
+    # guard), the second normalises what is left, so the column comes back as
+    # a unit vector orthogonal to Y and to the other columns
+    import torch
+    from oracle.gplhr_oracle import orth
+    from paper_1506_06829_amd import gplhr as G
+    rng = np.random.default_rng(11)
+    n, wy, w = 4099, 16, 16
+    Z = _block(rng, n, wy + w)
+    Z[:, :wy] = orth(Z[:, :wy])
+    Z[:, wy + 3] = Z[:, :wy] @ rng.standard_normal(wy)
+    Zd = torch.as_tensor(Z).to(device)
+    G.proj_orth(Zd, wy, w, passes=2)
+    Q = Zd.cpu().numpy()[:, wy:]
+    assert np.max(np.abs(Q.conj().T @ Q - np.eye(w))) < 1e-13
+    assert np.max(np.abs(Z[:, :wy].conj().T @ Q)) < 1e-13
+    # the other columns are those of the QR factorisation with that column
+    # taken out of the block
+    keep = [c for c in range(w) if c != 3]
+    X = Z[:, wy:][:, keep]
+    ref = orth(X - Z[:, :wy] @ (Z[:, :wy].conj().T @ X))
+    assert np.linalg.norm(Q[:, [0, 1, 2]] - ref[:, :3]) < 1e-12
+
+
 def test_block_update_rejects_oversized_coefficients(device):
     import torch
     from paper_1506_06829_amd import gplhr as G
