@@ -728,7 +728,7 @@ def main():
         threads = max([b["threads"] for b in (info["blas"] or []) if b.get("threads")] or [1])
         cpu = {"value": t_one, "unit": "s/iteration", "cores": threads, "kind": "oracle",
                "sample": f"the FP64 oracle (numpy/scipy) on the same 160^3 workload: set-up "
-                         f"(steps 1-4 of Algorithm 2, {t_setup:.1f} s) and one GPLHR iteration "
+                         f"(the initialisation of Algorithm 2, {t_setup:.1f} s) and one GPLHR iteration "
                          f"({t_one:.1f} s); scipy.sparse products single-threaded, dense BLAS "
                          f"on {threads} threads",
                "setup_s": t_setup, "host": info,

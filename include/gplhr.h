@@ -94,8 +94,8 @@ typedef struct {
 
 enum { GPLHR_FP64 = 0, GPLHR_MIXED = 1 };
 /* Additional search directions P (Section 3.4): thick restart P = Z Ybar_R(:, b+1:2b)
- * (eq. P1, the paper's default), the previous V (with the projections of step 22
- * this spans the same space as the LOBPCG-style eq. P_lobpcg), or none. */
+ * (eq. P1, the paper's default), the previous V (with the projections of P against
+ * V, W and S in Algorithm 2 this spans the same space as the LOBPCG-style eq. P_lobpcg), or none. */
 enum { GPLHR_P_THICK = 0, GPLHR_P_LOBPCG = 1, GPLHR_P_NONE = 2 };
 /* Iterated form: Schur vectors (Algorithm 2, the default) or approximate
  * eigenvectors with Rayleigh-quotient eigenvalues (GPLHR-EIG, Algorithm 3 of
@@ -168,7 +168,7 @@ void gplhr_default_options(gplhr_options *opt);
 
 /* Set up the operator C = A - sigma B on the union sparsity pattern, its
  * diagonal, the preconditioner and all device workspace, then run the
- * initialisation of Algorithm 2 (steps 1-4: V = orth(V0), Q = orth(C V),
+ * initialisation of Algorithm 2 (V = orth(V0), Q = orth(C V),
  * ordered QZ of (Q^H A V, Q^H B V), rotation of V and Q, M_A and M_B of
  * eq. M with G1, G2 of eqs. G1_fix, G2_fix).
  *
@@ -195,7 +195,7 @@ gplhr_status gplhr_create(const gplhr_csr *A, const gplhr_csr *B,
                           const gplhr_precond *T, const gplhr_options *opt,
                           gplhr_t *out);
 
-/* Run GPLHR iterations (Algorithm 2, steps 5-31) until the convergence test
+/* Run GPLHR iterations (the main loop of Algorithm 2) until the convergence test
  * of gplhr_options.tol holds or max_iter iterations have run (max_iter <= 0:
  * use opt.max_iter).  n_converged (may be NULL) receives the number of leading
  * pairs that meet tol; max_rel_resid (may be NULL) the largest relative
@@ -385,7 +385,8 @@ gplhr_status gplhr_gram_noalloc(int dtype, int64_t n, const void *X, int ldx, in
 
 /* Y = T R for the damped Jacobi preconditioner on C: T approximates C^{-1}
  * for C = A - sigma B, as Section 4 asks of the preconditioner that Algorithm
- * 2 applies in its steps 8 and 15.  From w_0 = 0, sweeps steps of
+ * 2 applies to the residual block and to each Krylov block.  From w_0 = 0,
+ * sweeps steps of
  * w <- w + omega diag(C)^{-1} (R - C w) (the first one is omega diag(C)^{-1} R,
  * so sweeps - 1 sparse products); the same kernels as the solver's
  * GPLHR_PRECOND_JACOBI.  C is a device CSR (n, nnz, row_ptr, col_idx with

@@ -97,7 +97,7 @@ def _dist(a: complex, b: complex, sigma: complex) -> float:
 
 def ordqz(F: np.ndarray, G: np.ndarray, sigma: complex):
     """Full generalized Schur form of (F, G), ordered so that
-    |R_A(i,i)/R_B(i,i) - sigma| is non-decreasing (footnote to step 2 of
+    |R_A(i,i)/R_B(i,i) - sigma| is non-decreasing (the ordering footnote of
     Algorithm 2).  Returns (R_A, R_B, Y_L, Y_R) with F Y_R = Y_L R_A and
     G Y_R = Y_L R_B."""
     RA, RB, YL, YR = sla.qz(F, G, output="complex")
@@ -375,10 +375,10 @@ def gplhr(A, B, sigma: complex, k: int, V0: np.ndarray, precond: Callable,
     k        number of wanted eigenpairs; the block width b = V0.shape[1] >= k.
     precond  callable applying T ~ (A - sigma B)^{-1} to a block.
     m        Krylov-Arnoldi depth (number of S blocks).
-    p_mode   "thick":  P = Z Ybar_R(:, b+1:2b) (eq. P1, step 28);
+    p_mode   "thick":  P = Z Ybar_R(:, b+1:2b) (eq. P1);
              "lobpcg": P = the previous V (eq. P_lobpcg: V^(i) - V^(i-1) C_V spans,
                        together with V^(i), the same space; the projections of
-                       step 22 then turn it into that direction);
+                       P against V, W and S then turn it into that direction);
              "none":   no P block (trial space of eq. trial_partial).
     proj_before_T  apply (I - QQ^*) (B = I: (I - VV^*)) before T, as in eqs.
              prec_gen / prec; False gives the variant of Table 3 without it.
@@ -515,8 +515,9 @@ def gplhr_eig(A, B, sigma: complex, k: int, X0: np.ndarray, precond: Callable,
     columns are iterated; the k leading ones decide convergence, measured by
     ||A x_j - lambda_j B x_j|| / ||A x_j|| at the Rayleigh quotient lambda_j.
 
-    p_mode  "thick":  P = Z Ybar(:, b+1:2b) (step 26);
-            "lobpcg": P = W Y_W + S Y_S + P Y_P (step 25 kept, step 26 off);
+    p_mode  "thick":  P = Z Ybar(:, b+1:2b) (the thick restart of Algorithm 3);
+            "lobpcg": P = W Y_W + S Y_S + P Y_P (Algorithm 3's LOBPCG-style
+                      direction, without the thick restart);
             "none":   no P block.
     Reading: the test-basis step projects against Q before orthonormalising
     (as for Algorithm 2).

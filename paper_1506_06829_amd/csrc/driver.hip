@@ -403,9 +403,10 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     const int nkeep = std::min(thick ? b + p_cols : b, s_cur);
     const int offP = smax - b;
     if (eig) {
-        // Algorithm 3, steps 22-26: eigenvectors Ybar of the projected pencil
-        // nearest sigma; X = Z Ybar(:, 1:b), P = Z Ybar(:, b+1:b+p) (thick) or
-        // P = [W S P] Ybar(b+1:s, 1:b) (LOBPCG-style, step 25)
+        // Algorithm 3, the harmonic Rayleigh-Ritz step: eigenvectors Ybar of
+        // the projected pencil nearest sigma; X = Z Ybar(:, 1:b),
+        // P = Z Ybar(:, b+1:b+p) (thick) or P = [W S P] Ybar(b+1:s, 1:b)
+        // (LOBPCG-style)
         Mat Yb;
         if (!small::harmonic_eig(K, Gm, nkeep, Yb)) throw singular();
         small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -424,7 +425,8 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
         t.ld = ld; t.col = 0; t.w = s_cur; t.M = coefY; t.ldm = s_cur;
         t.in = w.Z;
         update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
-        // C V and B V only: C P and B P are formed afresh after step 18
+        // C V and B V only: C P and B P are formed afresh once P is
+        // orthonormalised
         t.in = w.CZ;
         update<T>(w.CZ, ld, b, 0, b, offP, false, 1, &t);
         if (bexp()) {
@@ -440,7 +442,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     small_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     RA = r.RA; RB = r.RB; MA = r.MA; MB = r.MB;
     // coefficients: [Y_R | Y_P] (s_cur x nc), Y_L (s_cur x b), M1 = M_B, M2 = sigma M_B - M_A.
-    // Y_P is Ybar_R(:, b+1:b+p) for the thick restart (step 29), or, for the
+    // Y_P is Ybar_R(:, b+1:b+p) for the thick restart (eq. P1), or, for the
     // LOBPCG-style direction, the unit vectors that pick the active columns of
     // the current V, so that one row-local update produces V_new and P = V_old.
     int nc = r.ncols;
@@ -474,7 +476,8 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     t.ld = ld; t.col = 0; t.w = s_cur; t.M = cY; t.ldm = s_cur;
     t.in = w.Z;
     update<T>(w.Z, ld, nc, 0, b, offP, false, 1, &t);
-    // C V and B V only: C P and B P are formed afresh after step 22
+    // C V and B V only: C P and B P are formed afresh once P is
+    // orthonormalised
     t.in = w.CZ;
     update<T>(w.CZ, ld, b, 0, b, offP, false, 1, &t);
     if (bexp()) {
@@ -488,7 +491,7 @@ void Ctx::srr_and_update(int s_cur, int p_cols) {
     pw = nc - b;
 }
 
-// Steps 1-4 of Algorithm 2 from Z(:, 0:w0) (V0, or [V P] when restarting in
+// The initialisation of Algorithm 2 from Z(:, 0:w0) (V0, or [V P] when restarting in
 // another precision): orthonormalise, C Z, U = orth(C Z), ordered QZ, rotate.
 // check_rank: reject a numerically rank-deficient V0 (BREAKDOWN).
 template <typename T>
@@ -524,8 +527,8 @@ void Ctx::init_from_Z(int w0, bool check_rank) {
 
 // Algorithm 3 bookkeeping on the device: the new X in Z(:, 0:b) becomes
 // X = V Rx with V orthonormal (two Cholesky-QR passes, mirrored onto C X and
-// B X) and Rx scaled to unit-norm columns of X (step 27); Q = orth(C V), whose
-// span is that of C X (step 4).
+// B X) and Rx scaled to unit-norm columns of X; Q = orth(C V), whose span is
+// that of C X (Algorithm 3).
 template <typename T>
 void Ctx::eig_orthonormalise() {
     Work<T> &w = W<T>();
@@ -558,7 +561,7 @@ void Ctx::eig_orthonormalise() {
     }
 }
 
-// Steps 1-2 of Algorithm 3 from X = Z(:, 0:b) (X0, or the current X when the
+// The initialisation of Algorithm 3 from X = Z(:, 0:b) (X0, or the current X when the
 // FP64 phase begins): C X (and B X), X = V Rx, Q = orth(C V); P empty.
 template <typename T>
 void Ctx::init_eig() {
@@ -571,7 +574,7 @@ void Ctx::init_eig() {
     pw = 0;
 }
 
-// One GPLHR iteration (Algorithm 2, steps 6-31), with soft locking of the q
+// One GPLHR iteration (one pass of the loop of Algorithm 2), with soft locking of the q
 // leading columns when enabled.
 template <typename T>
 void Ctx::iterate_once() {
@@ -584,7 +587,7 @@ void Ctx::iterate_once() {
     const int pa = std::min(pw, a);            // P columns used (first ones kept)
     const int s_cur = pos + pa;
     T *Z = w.Z, *CZ = w.CZ, *BZ = w.BZ, *U = w.U;
-    // left projector basis: Q when B != I, V when B = I (steps 8/10, 15/17)
+    // left projector basis: Q when B != I, V when B = I (eqs. prec_gen / prec)
     const T *Lb = (bk == B_IDENT) ? Z : U;
     const T *bsc = bscale<T>();
 
@@ -610,11 +613,11 @@ void Ctx::iterate_once() {
         bprod<T>(Z + dst, ld, BZ + dst, ld, a);
     };
     const double2 *m1 = eig ? M1 : M1c, *m2 = eig ? M2 : M2c;
-    build(0, b, m1, m2, q * b, offW);                                // W (steps 6-12)
-    for (int l = 1; l <= m_cur; ++l)                                  // S_l (steps 13-21)
+    build(0, b, m1, m2, q * b, offW);                                // W
+    for (int l = 1; l <= m_cur; ++l)                                  // S_1 .. S_m
         build(offW + (l - 1) * a, a, eig ? M1s : m1, eig ? M2s : m2, q + q * b, offW + l * a);
 
-    // step 22: P <- orth(P - [V W S][V W S]^H P), then C P (and B P)
+    // P <- orth(P - [V W S][V W S]^H P), then C P (and B P)
     if (pa > 0) {
         T *bz = bexp() ? BZ : nullptr;
         if (pos != offPs) {
@@ -631,7 +634,7 @@ void Ctx::iterate_once() {
         cprod<T>(Z + pos, ld, CZ + pos, ld, pa);
         bprod<T>(Z + pos, ld, BZ + pos, ld, pa);
     }
-    // steps 23-24: U = [Q, orth((I - Q Q^H) C [W S P])].  First pass from
+    // test basis U = [Q, orth((I - Q Q^H) C [W S P])].  First pass from
     // X = C [W S P]: the Grams Q^H X and X^H X into one (b + wq)-by-wq array,
     // the projected Cholesky factor, and U(:, b:) = X Rinv + Q Cy; the second
     // pass on U itself.
@@ -649,14 +652,15 @@ void Ctx::iterate_once() {
         update<T>(U, ld, wq, b, wq, 0, false, 2, t);
     }
     proj_orth<T>(U, ld, 0, b, b, wq, 1);
-    // steps 25-31
+    // projected pencil, ordered Schur form, new V, Q, P (Section 3.5)
     srr_and_update<T>(s_cur, opt.p_mode == GPLHR_P_NONE ? 0 : a);
     ++n_iter;
     if (sizeof(T) == sizeof(double2)) ++n_iter64;
 }
 
 // Exact C V (and B V) by fresh sparse products: removes the drift of the
-// mirrored products (C P and B P are always formed afresh after step 22).
+// mirrored products (C P and B P are always formed afresh once P is
+// orthonormalised).
 template <typename T>
 void Ctx::refresh_products() {
     Work<T> &w = W<T>();
@@ -948,7 +952,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     }
     GPLHR_HIP_CHECK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
 
-    // V0 -> Z(:, 0:b), then steps 1-4
+    // V0 -> Z(:, 0:b), then the initialisation of Algorithm 2
     if (opt.V0)
         GPLHR_HIP_CHECK(hipMemcpy2DAsync(wd.Z, smax * sizeof(double2), opt.V0, b * sizeof(double2),
                                          b * sizeof(double2), n, hipMemcpyDeviceToDevice, st));
