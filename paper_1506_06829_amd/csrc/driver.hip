@@ -604,7 +604,13 @@ void Ctx::iterate_once() {
         t[1].in = bexp() ? BZ : Z; t[1].ld = ld; t[1].col = src; t[1].w = ws;
         t[1].M = m2 + moff; t[1].ldm = b; t[1].rowscale = bsc;
         update<T>(w.R, b, a, 0, a, 0, false, 2, t);
-        if (opt.proj_before_T) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
+        // The residual block of the Schur form needs no left projection when
+        // B != I: every ordered QZ step leaves Q^H A V = R_A and Q^H B V = R_B,
+        // and with G = R_A G1 + R_B G2 (eq. M) Q^H R = R_A M_B - R_B M_A = 0,
+        // so (I - Q Q^H) R = R up to rounding of the size R carries anyway.
+        // With B = I the left basis is V, for which this does not hold.
+        const bool q_orthogonal = src == 0 && !eig && bk != B_IDENT && !defl_k;
+        if (opt.proj_before_T && !q_orthogonal) project<T>(w.R, b, 0, a, Lb, ld, 0, b);
         apply_T<T>(Z, ld, dst, a);
         if (defl_k)
             for (int pass = 0; pass < 2; ++pass) deflate_right<T>(Z, ld, dst, a);

@@ -2158,39 +2158,32 @@ struct ResidArgs {
 
 // Residual norms of the Ritz pairs (x_j = V z_j, A x_j = (C + sigma B) V z_j):
 // per column j, sum over rows of |A x_j - lambda_j B x_j|^2 and |A x_j|^2, in
-// FP64 for both block precisions.  A x and B x come from one real-split GEMM
-// on the FP64 MFMA, as in the block update: the inputs are [C V | B V] (or
-// V with the diagonal of B as a row scale), the coefficients [[Z, 0],
-// [sigma Z, Z]], so A x sits in output columns 0 .. pb-1 and B x in pb ..
-// 2 pb - 1 (pb = b rounded up to 8).  The lanes holding the real and the
-// imaginary part of one entry swap halves, each adds its rows to per-lane
+// FP64 for both block precisions.  y1 = (C V) Z and y2 = (B V) Z (or V with
+// the diagonal of B as a row scale) come from one real-split GEMM on the FP64
+// MFMA with the one coefficient tile Z, as in the block update; then
+// A x = y1 + sigma y2 and B x = y2.  A wavefront owns row groups of 16 rows
+// and loads every input slab of its next row group into a second register
+// buffer while it multiplies the current one.  The lanes holding the real and
+// the imaginary part of one entry swap halves, each adds its rows to per-lane
 // sums, and the block sums them in a fixed order into its partial.
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void resid_mfma_kernel(ResidArgs<T> a) {
-    constexpr int WOP = 8 * NT;           // 2 pb complex output columns
-    constexpr int PB = WOP / 2;
+__global__ __launch_bounds__(256) void resid_pipe_kernel(ResidArgs<T> a) {
+    constexpr int PB = 4 * NT;            // b rounded up to 8
     constexpr int NSL = PB / 8;           // slabs of 8 input columns per term
+    constexpr int NH = NT / 2;            // real 16-column tiles of y1 (and of y2)
     extern __shared__ double2 sh_resid_raw[];
-    double2 *sM = sh_resid_raw;           // 2 PB x WOP, row-major
+    double2 *sZ = sh_resid_raw;           // PB x PB, row = input column
     const int b = a.b;
-    for (int e = threadIdx.x; e < 2 * PB * WOP; e += 256) {
-        const int j = e / WOP, c = e - j * WOP;
-        double2 v = make_double2(0.0, 0.0);
-        if (j < PB) {
-            if (j < b && c < b) v = a.Zr[j + c * b];
-        } else if (j - PB < b) {
-            const int jj = j - PB;
-            if (c < b) v = cmul(a.sigma, a.Zr[jj + c * b]);
-            else if (c >= PB && c - PB < b) v = a.Zr[jj + (c - PB) * b];
-        }
-        sM[e] = v;
+    for (int e = threadIdx.x; e < PB * PB; e += 256) {
+        const int j = e / PB, c = e - j * PB;
+        sZ[e] = (j < b && c < b) ? a.Zr[j + c * b] : make_double2(0.0, 0.0);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const bool odd = li & 1;
-    double2 lamc[NT / 2];
+    double2 lamc[NH];
 #pragma unroll
-    for (int nt = 0; nt < NT / 2; ++nt) {
+    for (int nt = 0; nt < NH; ++nt) {
         const int c = nt * 8 + (li >> 1);
         lamc[nt] = c < b ? a.lam[c] : make_double2(0.0, 0.0);
     }
@@ -2198,125 +2191,104 @@ __global__ __launch_bounds__(256) void resid_mfma_kernel(ResidArgs<T> a) {
     const T *in1 = a.bv ? a.bv : a.V;
     const int ld1 = a.bv ? a.ldb : a.ldv;
     const bool scale1 = !a.bv && a.bscale;
-    const int64_t stride = (int64_t)gridDim.x * 64;
-    // slab q of a row group: term q / NSL (0: C V, 1: B V), slab q % NSL
-    struct Cur {
-        int64_t g;
-        int q;
-    };
-    auto next = [&](Cur c) {
-        if (++c.q == 2 * NSL) { c.q = 0; c.g += stride; }
-        return c;
-    };
-    T bx[2][2];
+    T xb[2][2][NSL][2];
     T brs[2];
-    auto load = [&](int p, const Cur &c) {
-        const int t = c.q / NSL, col0 = (c.q - t * NSL) * 8 + 2 * lk;
-        const int ca = col0 < b ? col0 : 0, cb = col0 + 1 < b ? col0 + 1 : 0;
-        int64_t row = c.g + li;
+    auto load = [&](int p, int64_t g) {
+        int64_t row = g + li;
         row = row < a.n ? row : a.n - 1;
-        const T *rp = t == 0 ? a.CV + row * a.ldc : in1 + row * ld1;
-        bx[p][0] = rp[ca];
-        bx[p][1] = rp[cb];
-        if (t == 1 && scale1) brs[p] = a.bscale[row];
+        if (scale1) brs[p] = a.bscale[row];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const T *rp = t == 0 ? a.CV + row * a.ldc : in1 + row * ld1;
+#pragma unroll
+            for (int sl = 0; sl < NSL; ++sl) {
+                const int col0 = sl * 8 + 2 * lk;
+                xb[p][t][sl][0] = rp[col0 < b ? col0 : 0];
+                xb[p][t][sl][1] = rp[col0 + 1 < b ? col0 + 1 : 0];
+            }
+        }
     };
-    d4v acc[NT];
+    double sr[NH], sa[NH];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = d4v{0.0, 0.0, 0.0, 0.0};
-    double sr[NT / 2], sa[NT / 2];
+    for (int nt = 0; nt < NH; ++nt) sr[nt] = sa[nt] = 0.0;
+    auto compute = [&](int p, int64_t g) {
+        d4v acc[2][NH];
 #pragma unroll
-    for (int nt = 0; nt < NT / 2; ++nt) sr[nt] = sa[nt] = 0.0;
-    auto multiply = [&](int p, const Cur &c) {
-        const int t = c.q / NSL, col0 = (c.q - t * NSL) * 8 + 2 * lk;
-        const double2 *mrow = sM + (int64_t)(t * PB + col0) * WOP + (li >> 1);
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            double2 m[NT];
+            for (int nt = 0; nt < NH; ++nt) acc[t][nt] = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) m[nt] = mrow[h * WOP + nt * 8];
-            double2 x = to_d(bx[p][h]);
-            if (t == 1 && scale1) x = cmul(to_d(brs[p]), x);
-            if (col0 + h >= b) x = make_double2(0.0, 0.0);
-            // C V (t = 0) has zero coefficients for the B x columns: its
-            // slabs run only the A x tiles (one branch per slab, none per MFMA)
-            if (t == 0) {
+        for (int t = 0; t < 2; ++t) {
 #pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    const double av = part == 0 ? x.x : x.y;
+            for (int sl = 0; sl < NSL; ++sl) {
+                const int col0 = sl * 8 + 2 * lk;
+                const double2 *mrow = sZ + col0 * PB + (li >> 1);
 #pragma unroll
-                    for (int nt = 0; nt < NT / 2; ++nt) {
-                        const double bv =
-                            part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
-                        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
-                    }
-                }
-            } else {
+                for (int h = 0; h < 2; ++h) {
+                    double2 m[NH];
 #pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    const double av = part == 0 ? x.x : x.y;
+                    for (int nt = 0; nt < NH; ++nt) m[nt] = mrow[h * PB + nt * 8];
+                    double2 x = to_d(xb[p][t][sl][h]);
+                    if (t == 1 && scale1) x = cmul(to_d(brs[p]), x);
+                    if (col0 + h >= b) x = make_double2(0.0, 0.0);
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const double bv =
-                            part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
-                        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nt], 0, 0, 0);
+                    for (int part = 0; part < 2; ++part) {
+                        const double av = part == 0 ? x.x : x.y;
+#pragma unroll
+                        for (int nt = 0; nt < NH; ++nt) {
+                            const double bv =
+                                part == 0 ? (odd ? m[nt].y : m[nt].x) : (odd ? m[nt].x : -m[nt].y);
+                            acc[t][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t][nt], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
-    };
-    auto finish = [&](int64_t g) {
+        // lane (li, lk) holds real column nt * 16 + li of rows 4 v + lk: the
+        // partner lane li ^ 1 holds the other part of the same entries
 #pragma unroll
-        for (int nt = 0; nt < NT / 2; ++nt) {
-            double oa[4], ob[4];
+        for (int nt = 0; nt < NH; ++nt) {
+            double o1[4], o2[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                oa[v] = __shfl_xor(acc[nt][v], 1);
-                ob[v] = __shfl_xor(acc[nt + NT / 2][v], 1);
+                o1[v] = __shfl_xor(acc[0][nt][v], 1);
+                o2[v] = __shfl_xor(acc[1][nt][v], 1);
             }
             const int c = nt * 8 + (li >> 1);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int v = 2 * u + (odd ? 1 : 0);
-                const int64_t row = g + 4 * v + lk;    // FP64 MFMA: register v holds row 4v + k
+                const int64_t row = g + 4 * v + lk;
                 if (row < a.n && c < b) {
-                    const double2 ax = odd ? make_double2(oa[v], acc[nt][v]) : make_double2(acc[nt][v], oa[v]);
-                    const double2 bxv = odd ? make_double2(ob[v], acc[nt + NT / 2][v])
-                                            : make_double2(acc[nt + NT / 2][v], ob[v]);
-                    const double2 r = csub(ax, cmul(lamc[nt], bxv));
+                    const double2 y1 = odd ? make_double2(o1[v], acc[0][nt][v]) : make_double2(acc[0][nt][v], o1[v]);
+                    const double2 y2 = odd ? make_double2(o2[v], acc[1][nt][v]) : make_double2(acc[1][nt][v], o2[v]);
+                    const double2 ax = cadd(y1, cmul(a.sigma, y2));
+                    const double2 r = csub(ax, cmul(lamc[nt], y2));
                     sr[nt] += r.x * r.x + r.y * r.y;
                     sa[nt] += ax.x * ax.x + ax.y * ax.y;
                 }
             }
         }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = d4v{0.0, 0.0, 0.0, 0.0};
     };
-    Cur c{((int64_t)blockIdx.x * 4 + wave) * 16, 0};
-    Cur q[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        q[p] = c;
-        if (c.g < a.n) load(p, c);
-        c = next(c);
+    const int64_t stride = (int64_t)gridDim.x * 64;
+    int64_t g = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    if (g < a.n) load(0, g);
+    while (g < a.n) {
+        const int64_t g1 = g + stride;
+        if (g1 < a.n) load(1, g1);
+        compute(0, g);
+        g = g1;
+        if (g >= a.n) break;
+        const int64_t g2 = g + stride;
+        if (g2 < a.n) load(0, g2);
+        compute(1, g);
+        g = g2;
     }
-    while (q[0].g < a.n) {
+    __syncthreads();   // sZ is reused for the block reduction
+    double2 *red = sh_resid_raw;   // [wave][lane][NH]
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const Cur cc = q[p];
-            if (cc.g < a.n) {
-                multiply(p, cc);
-                if (cc.q == 2 * NSL - 1) finish(cc.g);
-                q[p] = c;
-                if (c.g < a.n) load(p, c);
-                c = next(c);
-            }
-        }
-    }
-    __syncthreads();   // sM is reused for the block reduction
-    double2 *red = sh_resid_raw;   // [wave][lane][NT / 2]
-#pragma unroll
-    for (int nt = 0; nt < NT / 2; ++nt)
-        red[(wave * 64 + lane) * (NT / 2) + nt] = make_double2(sr[nt], sa[nt]);
+    for (int nt = 0; nt < NH; ++nt)
+        red[(wave * 64 + lane) * NH + nt] = make_double2(sr[nt], sa[nt]);
     __syncthreads();
     if ((int)threadIdx.x < b) {
         const int j = threadIdx.x, nt = j / 8, lh = j % 8;
@@ -2324,7 +2296,7 @@ __global__ __launch_bounds__(256) void resid_mfma_kernel(ResidArgs<T> a) {
         for (int w = 0; w < 4; ++w)
             for (int k = 0; k < 4; ++k)
                 for (int o = 0; o < 2; ++o)
-                    s2 = cadd(s2, red[(w * 64 + 2 * lh + o + 16 * k) * (NT / 2) + nt]);
+                    s2 = cadd(s2, red[(w * 64 + 2 * lh + o + 16 * k) * NH + nt]);
         a.part[(int64_t)j * a.nblk + blockIdx.x] = s2;
     }
 }
@@ -2340,11 +2312,12 @@ int launch_resid_partials(hipStream_t st, int64_t n, int b, const T *CV, int ldc
     a.nblk = nblk;
     a.rows_per_blk = 0;
     const int pb = pad8(b), nt = pb / 4;
-    const size_t shmem = std::max(sizeof(double2) * 2 * pb * 2 * pb, sizeof(double2) * 256 * (nt / 2));
+    // the coefficient tile, then the block's per-lane sums
+    const size_t shmem = sizeof(double2) * std::max(pb * pb, 256 * (nt / 2));
     if (nt == 2)
-        hipLaunchKernelGGL((resid_mfma_kernel<T, 2>), dim3(nblk), dim3(256), shmem, st, a);
+        hipLaunchKernelGGL((resid_pipe_kernel<T, 2>), dim3(nblk), dim3(256), shmem, st, a);
     else
-        hipLaunchKernelGGL((resid_mfma_kernel<T, 4>), dim3(nblk), dim3(256), shmem, st, a);
+        hipLaunchKernelGGL((resid_pipe_kernel<T, 4>), dim3(nblk), dim3(256), shmem, st, a);
     GPLHR_HIP_CHECK(hipGetLastError());
     return nblk;
 }

@@ -461,6 +461,14 @@ def test_iteration_invariants():
         x1 -= Q @ (Q.conj().T @ x1)
         x2 -= Q @ (Q.conj().T @ x2)
         np.testing.assert_allclose(x1, x2, atol=1e-10 * np.abs(x2).max())
+        # ... and the residual block needs no left projection at all: with
+        # Q^H A V = R_A, Q^H B V = R_B and G = R_A G1 + R_B G2 of eq. M,
+        # Q^H (A V M_B - B V M_A) = R_A M_B - R_B M_A = 0 (the projection
+        # removes rounding only)
+        np.testing.assert_allclose(st["RA"] @ MB - st["RB"] @ MA, 0,
+                                   atol=1e-12 * np.abs(st["RA"]).max())
+        scale = np.abs(A @ V).max() * max(np.abs(MA).max(), np.abs(MB).max())
+        assert np.abs(Q.conj().T @ (A @ V @ MB - B @ V @ MA)).max() < 1e-10 * scale
         assert Z.shape[1] in (3 * b, 4 * b)
 
 
