@@ -1017,8 +1017,17 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
     else if (a.MT == 4) {
         if (tall) gram_launch_variant<T, 4, 4, 2, 2>(st, a, part_cap, out, ldo, 512);
         else gram_launch_variant<T, 4, 4, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
-    } else if (a.MT == 5)   // two K steps in flight: more would spill registers
-        gram_launch_variant<T, 5, 5, 2, 1>(st, a, part_cap, out, ldo, nb);
+    } else if (a.MT == 5) {
+        // 40-column X (a 10-wide block's pencil and test-basis Grams).  Below
+        // 2^20 rows, 512 blocks: 5 N tiles as two column groups of 3 built for
+        // two waves per SIMD, 3 or 4 N tiles as groups of 2 with four K steps
+        // in flight (262144 rows: 40 x 40 complex128 137 -> 115 us, complex64
+        // 132 -> 105 us; 40 x 30 complex64 126 -> 89 us).  Tall blocks keep
+        // the one-group layout with two K steps in flight (more would spill).
+        if (tall) gram_launch_variant<T, 5, 5, 2, 1>(st, a, part_cap, out, ldo, nb);
+        else if (a.NT == 5) gram_launch_variant<T, 5, 3, 2, 2>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 5, 2, GM_PF, 1>(st, a, part_cap, out, ldo, 512);
+    }
     else if (a.MT == 6) {
         if (tall) gram_launch_variant<T, 6, 3, 2, 2>(st, a, part_cap, out, ldo, 512);
         else gram_launch_variant<T, 6, 3, GM_PF, 1>(st, a, part_cap, out, ldo, nb);

@@ -171,7 +171,8 @@ def test_csr_plane_of_unstructured_patterns(device):
         G.spmm(A, X, plane=24)
 
 
-@pytest.mark.parametrize("bx,by", [(1, 1), (5, 10), (10, 10), (16, 16), (30, 48), (48, 48), (64, 64)])
+@pytest.mark.parametrize("bx,by", [(1, 1), (5, 10), (10, 10), (16, 16), (30, 48), (48, 48), (64, 64),
+                                   (40, 40), (40, 30), (40, 24), (33, 37)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [1, 7, 1000, 100003])
 def test_gram_matches_definition(device, bx, by, dtype, n):
