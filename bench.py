@@ -43,8 +43,8 @@ DOMINANT_KERNEL_PROBE = "Gram c64 64x64"
 # read for a 256 MiB device copy), valid only for the kernels.hip whose
 # SHA-256 prefix is recorded with it; any later change to that file makes the
 # reported traffic null until the counters are taken again.
-DOMINANT_KERNEL_TRAFFIC = 4261225379          # bytes per launch
-DOMINANT_KERNEL_TRAFFIC_SRC = "0b9435e353a417e6"   # sha256 prefix of kernels.hip
+DOMINANT_KERNEL_TRAFFIC = 4261223684          # bytes per launch
+DOMINANT_KERNEL_TRAFFIC_SRC = "ec0454d6b8b86b9a"   # sha256 prefix of kernels.hip
 
 
 def kernels_source_sha():

@@ -689,10 +689,12 @@ void Ctx::check() {
     const int ld = smax;
     const T *bsrc = bexp() ? w.BZ : w.Z;
     const T *bsc = bscale<T>();
-    // the two Grams side by side in g0, so they come back in one copy
+    // V^H C V and V^H B V side by side in g0, from one pass over V, so they
+    // come back in one copy
     const size_t bb = (size_t)b * b;
-    gram<T>(w.Z, ld, b, w.CZ, ld, b, nullptr, g0);
-    gram<T>(w.Z, ld, b, bsrc, ld, b, bsc, g0 + bb);
+    tbegin(T_GRAM);
+    launch_gram2<T>(st, n, w.Z, ld, b, w.CZ, ld, b, bsrc, ld, b, bsc, part, PART_CAP, g0, b);
+    tend(T_GRAM);
     GPLHR_HIP_CHECK(hipMemcpyAsync(hpin, g0, 2 * bb * sizeof(double2), hipMemcpyDeviceToHost, st));
     GPLHR_HIP_CHECK(hipStreamSynchronize(st));
     Mat Va(b, b), Vb(b, b);

@@ -60,6 +60,13 @@ template <typename T>
 void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y, int ldy,
                  int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo);
 
+// [X^H Y1, X^H diag(yscale2) Y2] (bx-by-(by1 + by2)) in one pass over X, the
+// same kernels and reduction order as launch_gram; yscale2 may be null.
+template <typename T>
+void launch_gram2(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y1, int ldy1,
+                  int by1, const T *Y2, int ldy2, int by2, const T *yscale2, double2 *part,
+                  size_t part_cap, double2 *out, int ldo);
+
 // out[p + q*ldo] = sum_blk part[(p + q*bx) * nblk + blk]  (fixed order)
 void launch_reduce_partials(hipStream_t st, const double2 *part, int nblk, int bx, int by,
                             double2 *out, int ldo);

@@ -446,6 +446,9 @@ int spmm_plane(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci) 
 // an operand is used, so nothing waits on a load before its turn.  Row splits
 // are summed in LDS in a fixed order, and each block writes a real partial
 // Gram of its contiguous row range.
+// Y2 (optional): Y's columns from by1 on come from Y2 (leading dimension
+// ldy2) and only they take the row scale, so two Grams with the same X,
+// X^H Y and X^H diag(s) Y2, are one pass over X.
 template <typename T>
 struct GramMArgs {
     int64_t n;
@@ -460,6 +463,9 @@ struct GramMArgs {
     int nblk;
     int64_t rows_per_blk;
     int MT, NT, G, ks, NTg;
+    const T *Y2;
+    int ldy2;
+    int by1;
 };
 
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -518,7 +524,9 @@ void gram_mfma_kernel(GramMArgs<T> a) {
         for (int t = 0; t < NTC; ++t) {
             // the complex entry holding real column j
             const int j = (nt0 + t) * 16 + li;
-            const T yc = a.Y[rr * a.ldy + ((j < nby ? j : 0) >> 1)];
+            const int jc = (j < nby ? j : 0) >> 1;
+            const T *yp = (a.Y2 && jc >= a.by1) ? a.Y2 + rr * a.ldy2 + (jc - a.by1) : a.Y + rr * a.ldy + jc;
+            const T yc = *yp;
             yra[p][t] = yc.x;
             yia[p][t] = yc.y;
         }
@@ -542,7 +550,9 @@ void gram_mfma_kernel(GramMArgs<T> a) {
                     double v = 0.0;
                     if (okp && jr < nby) {
                         const double yr = yra[p][t], yi = yia[p][t];
-                        if (a.yscale)   // (sc * y), the real (jr even) or imaginary part
+                        // (sc * y), the real (jr even) or imaginary part
+                        const bool sc = a.yscale && (!a.Y2 || (jr >> 1) >= a.by1);
+                        if (sc)
                             v = (jr & 1) ? (scr[p] * yi + sci[p] * yr) : (scr[p] * yr - sci[p] * yi);
                         else
                             v = (jr & 1) ? yi : yr;
@@ -957,14 +967,15 @@ static void gram_launch_lds(hipStream_t st, const GramMArgs<T> &m, size_t part_c
 template <typename T>
 static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y,
                              int ldy, int by, const T *yscale, double2 *part, size_t part_cap,
-                             double2 *out, int ldo) {
+                             double2 *out, int ldo, const T *Y2 = nullptr, int ldy2 = 0, int by1 = 0) {
     if (bx < 1 || by < 1 || bx > 64 || by > 64) throw Error(-1, "gram: width out of range");
     if (n <= 0) throw Error(-1, "gram: empty block");
+    const bool two = Y2 != nullptr;
     // X at most 16 columns against a wider Y (no row scale): the product is
     // formed as Y^H X, whose narrow side is the one the tile sets are built
     // for, and written conjugate-transposed (16 x 48 at 4096000 rows: the
     // direct form runs a third of its M tiles on zeros)
-    if (!yscale && bx <= 16 && by > 16 && n >= ((int64_t)1 << 20)) {
+    if (!two && !yscale && bx <= 16 && by > 16 && n >= ((int64_t)1 << 20)) {
         GramMArgs<T> a{};
         a.n = n; a.X = Y; a.ldx = ldy; a.bx = by; a.Y = X; a.ldy = ldx; a.by = bx;
         a.part = reinterpret_cast<double *>(part);
@@ -980,6 +991,7 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
     GramMArgs<T> a{};
     a.n = n; a.X = X; a.ldx = ldx; a.bx = bx; a.Y = Y; a.ldy = ldy; a.by = by;
     a.yscale = yscale;
+    a.Y2 = Y2; a.ldy2 = ldy2; a.by1 = by1;
     a.part = reinterpret_cast<double *>(part);
     a.MT = (2 * bx + 15) / 16;
     a.NT = (2 * by + 15) / 16;
@@ -1012,6 +1024,13 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
             if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
             else gram_launch_variant<T, 8, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         }
+    } else if (two && a.MT <= 2 && a.NT <= 4) {
+        // [V^H C V, V^H B V] of a 16-wide block (4096000 rows): complex64
+        // 2 x 4 tiles per wave (590 us, the two Grams apart 707 us), complex128
+        // 2 x 2 with two column groups (638 against 733 us); the 3 x 3 set
+        // would run a third of its tiles on zeros (1085 / 1198 us)
+        if constexpr (sizeof(T) == 8) gram_launch_variant<T, 2, 4, GM_PF, 1>(st, a, part_cap, out, ldo, 512);
+        else gram_launch_variant<T, 2, 2, GM_PF, 1>(st, a, part_cap, out, ldo, 512);
     } else if (a.MT <= 3)
         gram_launch_variant<T, 3, 3, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     else if (a.MT == 4) {
@@ -1034,7 +1053,7 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
     } else {
         // (Y wider than 32 columns: at 64 x 32 the register-streaming kernel
         // measured faster, 1219 against 1320 us for complex64)
-        if (tall && a.NT > 4) gram_launch_lds<T>(st, a, part_cap, out, ldo);
+        if (tall && a.NT > 4 && !two) gram_launch_lds<T>(st, a, part_cap, out, ldo);
         else if (tall) gram_launch_variant<T, 8, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
         else gram_launch_variant<T, 8, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
     }
@@ -1044,6 +1063,20 @@ void launch_gram(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T
                  int by, const T *yscale, double2 *part, size_t part_cap, double2 *out, int ldo) {
     launch_gram_impl<T>(st, n, X, ldx, bx, Y, ldy, by, yscale, part, part_cap, out, ldo);
 }
+template <typename T>
+void launch_gram2(hipStream_t st, int64_t n, const T *X, int ldx, int bx, const T *Y1, int ldy1,
+                  int by1, const T *Y2, int ldy2, int by2, const T *yscale2, double2 *part,
+                  size_t part_cap, double2 *out, int ldo) {
+    if (!Y1 || !Y2 || by1 < 1 || by2 < 1) throw Error(-1, "gram: two-part Y needs both parts");
+    launch_gram_impl<T>(st, n, X, ldx, bx, Y1, ldy1, by1 + by2, yscale2, part, part_cap, out, ldo,
+                        Y2, ldy2, by1);
+}
+template void launch_gram2<double2>(hipStream_t, int64_t, const double2 *, int, int, const double2 *,
+                                    int, int, const double2 *, int, int, const double2 *, double2 *,
+                                    size_t, double2 *, int);
+template void launch_gram2<float2>(hipStream_t, int64_t, const float2 *, int, int, const float2 *, int,
+                                   int, const float2 *, int, int, const float2 *, double2 *, size_t,
+                                   double2 *, int);
 template void launch_gram<double2>(hipStream_t, int64_t, const double2 *, int, int,
                                    const double2 *, int, int, const double2 *, double2 *, size_t,
                                    double2 *, int);
