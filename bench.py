@@ -159,6 +159,17 @@ def kernel_rooflines(G, torch):
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
+    # the C ABI is called with its arguments marshalled once, so the loop
+    # times the kernels rather than the binding's per-call Python work
+    L = G.lib()
+    sp = G._stream_ptr()
+
+    def checked(call):
+        st = call()
+        if st != 0:
+            raise RuntimeError(f"probe call failed with status {st}")
+        return call
+
     out = []
     gen = torch.Generator(device="cuda")
     gen.manual_seed(5)
@@ -169,9 +180,11 @@ def kernel_rooflines(G, torch):
         e = 16 if dt == "c128" else 8
         X = torch.randn(n, wx, dtype=tdt, device="cuda", generator=gen)
         Y = torch.randn(n, wy, dtype=tdt, device="cuda", generator=gen)
-        # stored column-major already, so the binding makes no copy per call
-        M = torch.randn(wy, wx, dtype=torch.complex128, device="cuda", generator=gen).t()
-        ms = timed(lambda: G.block_update(X, M, Y, beta=beta))
+        # wx-by-wy coefficients, column-major
+        Mc = torch.randn(wy, wx, dtype=torch.complex128, device="cuda", generator=gen)
+        args = (0 if dt == "c128" else 1, n, G._ptr(X), X.stride(0), wx, G._ptr(Mc), wx, G._ptr(Y),
+                Y.stride(0), wy, float(beta), 0.0, sp)
+        ms = timed(checked(lambda: L.gplhr_block_update(*args)))
         nbytes = n * (wx + wy * (2 if beta else 1)) * e
         flops = 8.0 * n * wx * wy
         peak_tf = FP64_PEAK_TFLOPS if dt == "c128" else FP32_PEAK_TFLOPS
@@ -185,16 +198,19 @@ def kernel_rooflines(G, torch):
         if name.startswith(DOMINANT_KERNEL_PROBE) and DOMINANT_KERNEL_TRAFFIC_SRC == kernels_source_sha():
             rf["traffic"] = DOMINANT_KERNEL_TRAFFIC
         out.append(dict(kernel=name, n=n, ms=ms, bytes=nbytes, flops=flops, **rf))
-        del X, Y, M
+        del X, Y, Mc
     # (a 10 x 10 Gram at 262144 rows runs shorter than one call's host work,
-    # allocation of the partials included, so a loop of calls would time the
-    # host; its kernel time is in the rocprofv3 summary of the d1 solve)
+    # so a loop of calls would time the host; its kernel time is in the
+    # rocprofv3 summary of the d1 solve)
     for n, dt, bx, by in ((4096000, "c64", 64, 64), (4096000, "c128", 64, 64),
                           (4096000, "c128", 16, 16), (262144, "c128", 40, 40)):
         tdt = torch.complex128 if dt == "c128" else torch.complex64
         X = torch.randn(n, bx, dtype=tdt, device="cuda", generator=gen)
         Y = torch.randn(n, by, dtype=tdt, device="cuda", generator=gen)
-        ms = timed(lambda: G.gram(X, Y))
+        Gout = torch.empty((by, bx), dtype=torch.complex128, device="cuda")
+        args = (0 if dt == "c128" else 1, n, G._ptr(X), X.stride(0), bx, G._ptr(Y), Y.stride(0), by,
+                G._ptr(Gout), sp)
+        ms = timed(checked(lambda: L.gplhr_gram(*args)))
         nbytes = n * (bx + by) * (16 if dt == "c128" else 8)
         flops = 8.0 * n * bx * by
         t_mem, t_fl = nbytes / (HBM_PEAK_GBS * 1e6), flops / (FP64_PEAK_TFLOPS * 1e9)
@@ -207,7 +223,7 @@ def kernel_rooflines(G, torch):
         if name.startswith(DOMINANT_KERNEL_PROBE) and DOMINANT_KERNEL_TRAFFIC_SRC == kernels_source_sha():
             rf["traffic"] = DOMINANT_KERNEL_TRAFFIC
         out.append(dict(kernel=name, n=n, ms=ms, bytes=nbytes, flops=flops, **rf))
-        del X, Y
+        del X, Y, Gout
     torch.cuda.empty_cache()
     return out
 

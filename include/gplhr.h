@@ -327,7 +327,9 @@ gplhr_status gplhr_csr_plane(int64_t n, const int32_t *row_ptr, const int32_t *c
 /* G = X^H Y in complex128 (FP64 accumulation, deterministic order) for
  * row-major X (n-by-bx, ldx) and Y (n-by-by, ldy) of dtype 0 (complex128) or
  * 1 (complex64).  G is a device bx-by-by complex128 array, column-major.
- * 1 <= bx, by <= 64. */
+ * 1 <= bx, by <= 64.  Asynchronous on hip_stream.  The per-block partial sums
+ * go to a buffer the library keeps for each (device, stream) pair until the
+ * process ends (at most 64 MiB; growing it waits for the stream once). */
 gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx,
                         const void *Y, int ldy, int by, void *G, void *hip_stream);
 

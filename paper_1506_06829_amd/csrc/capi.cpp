@@ -40,6 +40,16 @@ gplhr_status guard(gplhr_t h, F &&f) {
 }
 }  // namespace
 
+// Partial sums of gplhr_gram: one buffer per (device, stream), grown on
+// demand and kept until the process ends.  Calls on one stream run in stream
+// order, so each may reuse the buffer the previous one filled; the lock is
+// held while a call enqueues its kernels, so a buffer is only replaced (after
+// its stream has drained) when no call is about to use it.
+namespace {
+std::mutex g_gram_mu;
+std::map<std::pair<int, hipStream_t>, std::pair<double2 *, size_t>> g_gram_part;
+}  // namespace
+
 extern "C" {
 
 void gplhr_default_options(gplhr_options *opt) {
@@ -374,8 +384,20 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
             throw gplhr::Error(-1, "gplhr_gram: bad arguments");
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         const size_t cap = (size_t)1024 * bx * by;
-        double2 *part = nullptr;
-        GPLHR_HIP_CHECK(hipMallocAsync((void **)&part, sizeof(double2) * cap, st));
+        int dev = 0;
+        GPLHR_HIP_CHECK(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lock(g_gram_mu);
+        auto &buf = g_gram_part[{dev, st}];
+        if (buf.second < cap) {
+            if (buf.first) {
+                GPLHR_HIP_CHECK(hipStreamSynchronize(st));
+                GPLHR_HIP_CHECK(hipFree(buf.first));
+                buf = {nullptr, 0};
+            }
+            GPLHR_HIP_CHECK(hipMalloc((void **)&buf.first, sizeof(double2) * cap));
+            buf.second = cap;
+        }
+        double2 *part = buf.first;
         if (dtype == 0)
             gplhr::launch_gram<double2>(st, n, static_cast<const double2 *>(X), ldx, bx,
                                         static_cast<const double2 *>(Y), ldy, by, nullptr, part,
@@ -384,7 +406,6 @@ gplhr_status gplhr_gram(int dtype, int64_t n, const void *X, int ldx, int bx, co
             gplhr::launch_gram<float2>(st, n, static_cast<const float2 *>(X), ldx, bx,
                                        static_cast<const float2 *>(Y), ldy, by, nullptr, part, cap,
                                        static_cast<double2 *>(G), bx);
-        GPLHR_HIP_CHECK(hipFreeAsync(part, st));
         return 0;
     });
 }
