@@ -855,7 +855,9 @@ __global__ __launch_bounds__(256) void reduce_real_partials_kernel(const double 
     const int jc = 2 * q + (v >> 4);   // real column
     double acc = 0.0;
     if (i < nbx) {
+        // eight loads in flight per thread; the additions keep their order
         const double *src = part + i + (int64_t)jc * nbx;
+#pragma unroll 8
         for (int blk = g; blk < nblk; blk += 8) acc += src[blk * E];
     }
     sh[g][v] = acc;
