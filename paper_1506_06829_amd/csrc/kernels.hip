@@ -1881,6 +1881,7 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     // its strict lower triangle then receives R^{-1} transposed (the diagonal
     // of R^{-1} goes to dinv).
     __shared__ double2 A[48 * 49];   // leading dimension w + 1: a row of A spreads over the LDS banks
+    __shared__ double2 GY[1024];     // G_Y (wy-by-w, column-major, ld wy): wy * w <= 1024
     __shared__ double dsc[48];
     __shared__ double rdiag[48];
     __shared__ double dinv[48];
@@ -1893,13 +1894,16 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
     } else {
         // G is [Y X]^H X ((wy + w)-by-w, leading dimension wy + w) for an
         // orthonormal Y: rows 0..wy-1 hold G_Y = Y^H X, the rest X^H X.  The
-        // Gram of the projected block (X - Y G_Y) is X^H X - G_Y^H G_Y.
+        // Gram of the projected block (X - Y G_Y) is X^H X - G_Y^H G_Y.  G_Y
+        // is read into LDS once (the sums below and Cy read it many times).
         const int ldg = wy + w;
+        for (int e = tid; e < wy * w; e += 256) GY[e] = G[e % wy + (size_t)(e / wy) * ldg];
+        __syncthreads();
         for (int e = tid; e < w * w; e += 256) {
             const int i = e % w, j = e / w;
             double2 v = G[wy + i + (size_t)j * ldg];
             for (int t = 0; t < wy; ++t) {
-                const double2 a = G[t + (size_t)i * ldg], c = G[t + (size_t)j * ldg];
+                const double2 a = GY[t + i * wy], c = GY[t + j * wy];
                 v.x -= a.x * c.x + a.y * c.y;   // conj(a) * c
                 v.y -= a.x * c.y - a.y * c.x;
             }
@@ -1919,12 +1923,10 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         }
         __syncthreads();
         if (flag < 0) {
-            const int ldg = wy + w;
             for (int e = tid; e < w * w; e += 256)
                 Rinv[e] = make_double2((e % w) == (e / w) ? 1.0 : 0.0, 0.0);
             for (int e = tid; e < wy * w; e += 256) {
-                const int r = e % wy, j = e / wy;
-                const double2 g = G[r + (size_t)j * ldg];
+                const double2 g = GY[e];
                 Cy[e] = make_double2(-g.x, -g.y);
             }
             return;
@@ -2037,14 +2039,13 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int w, const double2 *G,
         // Cy = -G_Y Rinv (wy-by-w, leading dimension wy): the coefficients of
         // Y in (X - Y G_Y) Rinv; Rinv(i, j) = dsc[i] * (dinv[i] if i == j,
         // A[j + i lda] if i < j)
-        const int ldg = wy + w;
         for (int e = tid; e < wy * w; e += 256) {
             const int r = e % wy, j = e / wy;
             double2 acc = make_double2(0.0, 0.0);
             for (int i = 0; i <= j; ++i) {
                 const double2 ri = (i == j) ? make_double2(dinv[i] * dsc[i], 0.0)
                                             : make_double2(A[j + i * lda].x * dsc[i], A[j + i * lda].y * dsc[i]);
-                const double2 g = G[r + (size_t)i * ldg];
+                const double2 g = GY[r + i * wy];
                 acc.x += g.x * ri.x - g.y * ri.y;
                 acc.y += g.x * ri.y + g.y * ri.x;
             }
