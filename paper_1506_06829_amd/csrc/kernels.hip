@@ -1015,8 +1015,13 @@ static void launch_gram_impl(hipStream_t st, int64_t n, const T *X, int ldx, int
         // 40 x 10 924 -> 633 us, 30 x 10 686 -> 526 us)
         if (a.MT <= 2) gram_launch_variant<T, 2, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         else if (a.MT == 3) gram_launch_variant<T, 3, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 4) gram_launch_variant<T, 4, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
-        else if (a.MT == 5) {
+        else if (a.MT == 4) {
+            // built for two waves per SIMD: 32 x 16 at 4096000 rows complex64
+            // 475 -> 373 us (1024 blocks), complex128 535 -> 529 us (512);
+            // 262144 rows 44 -> 39 and 46 -> 42 us (512)
+            const int nb4 = (tall && sizeof(T) == 8) ? 1024 : 512;
+            gram_launch_variant<T, 4, 2, 2, 2>(st, a, part_cap, out, ldo, nb4);
+        } else if (a.MT == 5) {
             if (tall) gram_launch_variant<T, 5, 2, 2, 2>(st, a, part_cap, out, ldo, 512);
             else gram_launch_variant<T, 5, 2, GM_PF, 1>(st, a, part_cap, out, ldo, nb);
         } else if (a.MT == 6) {
