@@ -26,8 +26,7 @@ Primitives:
                     (LAPACK ztgexc) so that |alpha/beta - sigma| ascends,
 * small matrices:   numpy dense FP64 complex.
 
-Readings taken where the paper is silent or inconsistent (each is listed in
-DESIGN.md as well):
+Readings taken where the paper is silent or inconsistent:
 
 * ``orth`` (footnote of Algorithm 1) is any orthonormalisation of the span; we
   use Householder QR and normalise to the Q factor whose triangular factor has
