@@ -319,12 +319,6 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 // operator (16 complex64 columns) keeps 8 (431 us; 17 slots: 564 us).
 template <typename T, int MODE, int BATCH>
 static void spmm_go(hipStream_t st, const SpmmArgs<T> &a, int cpl, int grid) {
-    if constexpr (sizeof(T) == 8) {
-        if (cpl == 4) {
-            hipLaunchKernelGGL((spmm_kernel<T, 4, MODE, BATCH>), dim3(grid), dim3(256), 0, st, a);
-            return;
-        }
-    }
     if (cpl == 2)
         hipLaunchKernelGGL((spmm_kernel<T, 2, MODE, BATCH>), dim3(grid), dim3(256), 0, st, a);
     else
@@ -349,16 +343,18 @@ void launch_spmm(hipStream_t st, int64_t n, const int32_t *rp, const int32_t *ci
     // an output block larger than the 256 MB Infinity Cache cannot stay there
     // until it is read again: stream it past the caches
     a.nt = ((double)n * b * sizeof(T) > 256.0 * 1024 * 1024) ? 1 : 0;
-    // lanes move 32 bytes of the block row: 4 complex64 or 2 complex128 values
+    // lanes move two complex values of the block row: 16 bytes (complex64)
+    // or 32 bytes (complex128).  For complex64 this beat four values (32
+    // bytes) per lane on the 160^3 operator with 16 columns, 380 -> 345 us
+    // (product), 446 -> 425 us and 527 -> 506 us (the Jacobi epilogues), at the
+    // same results: twice the lanes per row, at fewer registers per lane.
     const uintptr_t align = reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
                             (mode != 0 ? reinterpret_cast<uintptr_t>(Rhs) : 0);
     int cpl = 1;
     if constexpr (sizeof(T) == 8) {
-        const bool ok4 = (b % 4 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) &&
-                         (mode == 0 || ldr % 2 == 0) && align % 16 == 0;
         const bool ok2 = (b % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) &&
                          (mode == 0 || ldr % 2 == 0) && align % 16 == 0;
-        cpl = ok4 ? 4 : (ok2 ? 2 : 1);
+        cpl = ok2 ? 2 : 1;
     } else {
         cpl = (b % 2 == 0) ? 2 : 1;
     }
