@@ -423,6 +423,12 @@ gplhr_status gplhr_proj_orth(int dtype, int64_t n, void *Z, int ld, int wy, int 
         const size_t nG = (size_t)wg * w, nR = (size_t)w * w, nC = (size_t)std::max(wy, 1) * w;
         double2 *buf = nullptr;
         GPLHR_HIP_CHECK(hipMallocAsync((void **)&buf, sizeof(double2) * (cap + nG + nR + nC + 1), st));
+        // released on every path out, errors included
+        struct Release {
+            double2 *&p;
+            hipStream_t s;
+            ~Release() { if (p) (void)hipFreeAsync(p, s); }
+        } release{buf, st};
         double2 *part = buf, *G = buf + cap, *rinv = G + nG, *cy = rinv + nR;
         int *status = reinterpret_cast<int *>(cy + nC);
         GPLHR_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int), st));
@@ -444,6 +450,7 @@ gplhr_status gplhr_proj_orth(int dtype, int64_t n, void *Z, int ld, int wy, int 
         int pivots = 0;
         GPLHR_HIP_CHECK(hipMemcpyAsync(&pivots, status, sizeof(int), hipMemcpyDeviceToHost, st));
         GPLHR_HIP_CHECK(hipFreeAsync(buf, st));
+        buf = nullptr;
         GPLHR_HIP_CHECK(hipStreamSynchronize(st));
         if (pivots > 0)
             throw gplhr::Error(-4, "gplhr_proj_orth: a Cholesky pivot of the projected block vanished "
