@@ -43,8 +43,8 @@ DOMINANT_KERNEL_PROBE = "Gram c64 64x64"
 # read for a 256 MiB device copy), valid only for the kernels.hip whose
 # SHA-256 prefix is recorded with it; any later change to that file makes the
 # reported traffic null until the counters are taken again.
-DOMINANT_KERNEL_TRAFFIC = 4261206213          # bytes per launch
-DOMINANT_KERNEL_TRAFFIC_SRC = "6eae2280a1dd2e56"   # sha256 prefix of kernels.hip
+DOMINANT_KERNEL_TRAFFIC = 4261221332          # bytes per launch
+DOMINANT_KERNEL_TRAFFIC_SRC = "32cf1a236323714d"   # sha256 prefix of kernels.hip
 
 
 def kernels_source_sha():

@@ -544,8 +544,8 @@ namespace {
 // The same kernel sequence as the solver's preconditioner application.
 template <typename T>
 void jacobi_apply(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
-                  const T *val, const T *dw, int sweeps, const T *R, int ldr, T *Y, int ldy, int b,
-                  int plane) {
+                  const T *val, const T *valdw, const T *dw, int sweeps, const T *R, int ldr, T *Y,
+                  int ldy, int b, int plane) {
     if (sweeps == 1) {
         gplhr::launch_scale_rows<T>(st, n, b, R, ldr, dw, Y, ldy);
         return;
@@ -560,7 +560,7 @@ void jacobi_apply(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp, con
         const int nxt = cur == 0 ? 1 : 0;
         T *o = last ? Y : J[nxt];
         if (t == 1)
-            gplhr::launch_spmm<T>(st, n, rp, ci, val, R, ldr, o, last ? ldy : b, b, 2, R, ldr, dw,
+            gplhr::launch_spmm<T>(st, n, rp, ci, valdw, R, ldr, o, last ? ldy : b, b, 2, R, ldr, dw,
                                   plane, nnz);
         else
             gplhr::launch_spmm<T>(st, n, rp, ci, val, J[cur], b, o, last ? ldy : b, b, 1, R, ldr, dw,
@@ -596,23 +596,31 @@ gplhr_status gplhr_jacobi(int dtype, int64_t n, int64_t nnz, const int32_t *row_
         }
         double2 *dw = static_cast<double2 *>(gplhr::dev_alloc(sizeof(double2) * n, st));
         gplhr::launch_recip_scaled(st, n, dg, make_double2(omega, 0.0), dw);
+        // values of C diag(omega / diag(C)) for the first two sweeps in one pass
+        double2 *vdw = (sweeps > 1 && nnz) ? static_cast<double2 *>(gplhr::dev_alloc(sizeof(double2) * nnz, st))
+                                           : nullptr;
+        if (vdw) gplhr::launch_scale_cols(st, nnz, col_idx, v, dw, vdw);
         if (dtype == 0) {
-            jacobi_apply<double2>(st, n, nnz, row_ptr, col_idx, v, dw, sweeps,
+            jacobi_apply<double2>(st, n, nnz, row_ptr, col_idx, v, vdw, dw, sweeps,
                                   static_cast<const double2 *>(R), ldr, static_cast<double2 *>(Y),
                                   ldy, b, plane);
         } else {
-            // complex64 copies of the values and of omega / diag(C), as in the
-            // solver's complex64 phase
+            // complex64 copies of the values, of omega / diag(C) and of the
+            // scaled values, as in the solver's complex64 phase
             float2 *v32 = nnz ? static_cast<float2 *>(gplhr::dev_alloc(sizeof(float2) * nnz, st)) : nullptr;
+            float2 *vdw32 = vdw ? static_cast<float2 *>(gplhr::dev_alloc(sizeof(float2) * nnz, st)) : nullptr;
             float2 *dw32 = static_cast<float2 *>(gplhr::dev_alloc(sizeof(float2) * n, st));
             if (nnz) gplhr::launch_c128_to_c64_flat(st, nnz, v, v32);
+            if (vdw) gplhr::launch_c128_to_c64_flat(st, nnz, vdw, vdw32);
             gplhr::launch_c128_to_c64_flat(st, n, dw, dw32);
-            jacobi_apply<float2>(st, n, nnz, row_ptr, col_idx, v32, dw32, sweeps,
+            jacobi_apply<float2>(st, n, nnz, row_ptr, col_idx, v32, vdw32, dw32, sweeps,
                                  static_cast<const float2 *>(R), ldr, static_cast<float2 *>(Y),
                                  ldy, b, plane);
             if (v32) gplhr::dev_free(v32, st);
+            if (vdw32) gplhr::dev_free(vdw32, st);
             gplhr::dev_free(dw32, st);
         }
+        if (vdw) gplhr::dev_free(vdw, st);
         gplhr::dev_free(dg, st);
         gplhr::dev_free(dw, st);
         return 0;

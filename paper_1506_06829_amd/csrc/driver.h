@@ -23,6 +23,7 @@ struct Work {
     const T *bd = nullptr;     // diagonal of a diagonal B
     const T *dinv = nullptr;   // 1 / diag(C)
     const T *dw = nullptr;     // omega / diag(C)
+    const T *cvdw = nullptr;   // values of C diag(omega / diag(C)) (two Jacobi sweeps in one pass)
     T *Z = nullptr, *CZ = nullptr, *BZ = nullptr, *U = nullptr;   // n x smax
     T *R = nullptr, *J1 = nullptr, *J2 = nullptr;                  // n x b
     T *G = nullptr;                    // block GMRES basis, n x (steps+1) b
@@ -79,8 +80,8 @@ struct Ctx {
     double2 *b_val = nullptr;
     float2 *b_val32 = nullptr;
     int64_t b_nnz = 0;
-    double2 *bd = nullptr, *dinv = nullptr, *dw = nullptr;
-    float2 *bd32 = nullptr, *dinv32 = nullptr, *dw32 = nullptr;
+    double2 *bd = nullptr, *dinv = nullptr, *dw = nullptr, *cvdw = nullptr;
+    float2 *bd32 = nullptr, *dinv32 = nullptr, *dw32 = nullptr, *cvdw32 = nullptr;
 
     Work<double2> wd;
     Work<float2> wf;

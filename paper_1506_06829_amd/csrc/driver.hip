@@ -48,6 +48,7 @@ Ctx::~Ctx() {
     dfree(a_rp, st); dfree(a_ci, st); dfree(a_val, st);
     dfree(b_rp, st); dfree(b_ci, st); dfree(b_val, st); dfree(b_val32, st);
     dfree(bd, st); dfree(bd32, st); dfree(dinv, st); dfree(dinv32, st); dfree(dw, st); dfree(dw32, st);
+    dfree(cvdw, st); dfree(cvdw32, st);
     for (Work<double2> *w : {&wd}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     for (Work<float2> *w : {&wf}) { dfree(w->Z, st); dfree(w->CZ, st); dfree(w->BZ, st); dfree(w->U, st); dfree(w->R, st); dfree(w->J1, st); dfree(w->J2, st); dfree(w->G, st); dfree(w->Gz, st); dfree(w->Gx, st); dfree(w->Vd, st); dfree(w->Qd, st); }
     dfree(part, st); dfree(g0, st); dfree(g1, st); dfree(rinv, st); dfree(coefY, st); dfree(cpack, st);
@@ -193,7 +194,9 @@ template <typename T>
 void Ctx::spmm_c(const T *X, int ldx, T *Y, int ldy, int wc, int mode, const T *Rhs, int ldr) {
     Work<T> &w = W<T>();
     tbegin(T_SPMM);
-    launch_spmm<T>(st, n, c_rp, c_ci, w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw, c_plane, c_nnz);
+    if (mode == 2 && !w.cvdw) throw Error(-1, "spmm: the two-sweep product needs the values of C diag(dw)");
+    launch_spmm<T>(st, n, c_rp, c_ci, mode == 2 ? w.cvdw : w.cval, X, ldx, Y, ldy, wc, mode, Rhs, ldr, w.dw,
+                   c_plane, c_nnz);
     tend(T_SPMM);
     ++n_spmm;
     spmm_bytes += (double)c_nnz * (sizeof(T) + 4) + 4.0 * (n + 1) +
@@ -255,8 +258,8 @@ void Ctx::apply_inner(int kind, const T *in, int ldi, T *dest, int ldd, int wc) 
             launch_scale_rows<T>(st, n, wc, in, ldi, w.dw, dest, ldd);
             return;
         }
-        // w_1 and w_2 in one pass (SpMM mode 2 forms w_1 = dw .* r at the
-        // gathered rows), then one pass per further sweep
+        // w_1 and w_2 in one pass (SpMM mode 2: C w_1 = (C diag(dw)) r from
+        // the prescaled values), then one pass per further sweep
         T *cur = nullptr;
         for (int t = 1; t < pre.sweeps; ++t) {
             const bool last = (t == pre.sweeps - 1);
@@ -900,6 +903,11 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
     // workspace
     const size_t blk_s = (size_t)n * smax, blk_b = (size_t)n * b;
     wd.cval = c_val; wd.bval = b_val; wd.bd = bd; wd.dinv = dinv; wd.dw = dw;
+    if (dw && pre.sweeps > 1) {
+        dalloc(&cvdw, c_nnz, st);
+        launch_scale_cols(st, c_nnz, c_ci, c_val, dw, cvdw);
+        wd.cvdw = cvdw;
+    }
     dalloc(&wd.Z, blk_s, st); dalloc(&wd.CZ, blk_s, st); dalloc(&wd.U, blk_s, st);
     defl_k = opt.defl_k;
     if (defl_k < 0 || defl_k > 64) throw Error(-1, "defl_k must be in [0, 64]");
@@ -928,6 +936,7 @@ void Ctx::setup(const gplhr_csr *A, const gplhr_csr *B, cd sig, int k_, int b_,
         if (bk == B_DIAG) { dalloc(&bd32, n, st); launch_c128_to_c64_flat(st, n, bd, bd32); wf.bd = bd32; }
         if (dinv) { dalloc(&dinv32, n, st); launch_c128_to_c64_flat(st, n, dinv, dinv32); wf.dinv = dinv32; }
         if (dw) { dalloc(&dw32, n, st); launch_c128_to_c64_flat(st, n, dw, dw32); wf.dw = dw32; }
+        if (cvdw) { dalloc(&cvdw32, c_nnz, st); launch_c128_to_c64_flat(st, c_nnz, cvdw, cvdw32); wf.cvdw = cvdw32; }
         dalloc(&wf.Z, blk_s, st); dalloc(&wf.CZ, blk_s, st); dalloc(&wf.U, blk_s, st);
         if (bexp()) dalloc(&wf.BZ, blk_s, st);
         if (defl_k) {

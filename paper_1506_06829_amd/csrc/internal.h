@@ -39,7 +39,7 @@ void pinned_free(void *p, size_t bytes);
 // Y = C X (mode 0) or, for the damped Jacobi sweep, Y = X + dw .* (Rhs - C X)
 // (mode 1), where dw holds omega / C(i,i) per row; mode 2 is the first two
 // sweeps from zero, Y = w + dw .* (Rhs - C w) with w = dw .* Rhs, and takes X
-// = Rhs (ldx = ldr).  plane > 0 runs the rows
+// = Rhs (ldx = ldr) and in val the values of C diag(dw) (launch_scale_cols).  plane > 0 runs the rows
 // in the plane-slab order (plane rows per plane; must divide n and be a
 // multiple of 8), 0 in natural order; the result is the same.  nnz (the
 // stored entries, rp[n]) sets how many entries of a row are gathered at once;
@@ -164,6 +164,10 @@ int64_t extract_diag(hipStream_t st, int64_t n, const int32_t *rp, const int32_t
                      const double2 *val, double2 *d);
 // out[i] = num / d[i]
 void launch_recip_scaled(hipStream_t st, int64_t n, const double2 *d, double2 num, double2 *out);
+// Values of C diag(s) on C's pattern: out[e] = val[e] * s[ci[e]] (one rounding
+// per entry), for the two-sweep Jacobi product (launch_spmm mode 2).
+void launch_scale_cols(hipStream_t st, int64_t nnz, const int32_t *ci, const double2 *val,
+                       const double2 *s, double2 *out);
 // Conjugate transpose of a CSR (count / scan / scatter).  Allocates the result.
 void csr_conj_transpose(hipStream_t st, int64_t n, int64_t nnz, const int32_t *rp,
                         const int32_t *ci, const double2 *val, int32_t **trp, int32_t **tci,

@@ -149,10 +149,10 @@ struct SpmmArgs {
 
 // MODE 0: Y = C X; MODE 1: the damped Jacobi sweep Y = X + dw .* (Rhs - C X);
 // MODE 2: the first two sweeps from w_0 = 0 in one pass, Y = w + dw .* (Rhs -
-// C w) with w = dw .* Rhs formed on the fly (X is Rhs: every gathered row is
-// scaled by its own dw).  Compile-time, so the plain product carries no
-// epilogue registers.  BATCH entries of a row have their
-// block-row gathers in flight together.
+// C w) with w = dw .* Rhs: X is Rhs and val holds the values of C diag(dw)
+// (launch_scale_cols), so C w is gathered from Rhs directly.  Compile-time, so
+// the plain product carries no epilogue registers.  BATCH entries of a row
+// have their block-row gathers in flight together.
 //
 // Index/value stream through LDS: when the rows of a workgroup are
 // consecutive rows of the matrix (always in natural order; in the plane-slab
@@ -240,16 +240,6 @@ __global__ __launch_bounds__(256) void spmm_kernel(SpmmArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) x[u][c] = czero<T>();
             }
-        }
-        if constexpr (MODE == 2) {
-            // w_1 at the gathered rows: dw_j .* X_j (an empty slot reads row 0)
-            T s[BATCH];
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) s[u] = a.dw[j[u] >= 0 ? j[u] : 0];
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u)
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) x[u][c] = cmul(s[u], x[u][c]);
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u)
@@ -2660,6 +2650,19 @@ __global__ void recip_kernel(int64_t n, const double2 *d, double2 num, double2 *
 }
 void launch_recip_scaled(hipStream_t st, int64_t n, const double2 *d, double2 num, double2 *out) {
     hipLaunchKernelGGL(recip_kernel, dim3(ceil_div_i(n, 256)), dim3(256), 0, st, n, d, num, out);
+    GPLHR_HIP_CHECK(hipGetLastError());
+}
+
+__global__ void scale_cols_kernel(int64_t nnz, const int32_t *ci, const double2 *val, const double2 *s,
+                                  double2 *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) out[e] = cmul(val[e], s[ci[e]]);
+}
+void launch_scale_cols(hipStream_t st, int64_t nnz, const int32_t *ci, const double2 *val,
+                       const double2 *s, double2 *out) {
+    if (nnz <= 0) return;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(ceil_div_i(nnz, 256)), dim3(256), 0, st, nnz, ci, val, s,
+                       out);
     GPLHR_HIP_CHECK(hipGetLastError());
 }
 
